@@ -1,0 +1,236 @@
+"""CPU oracle for PSA alias-table construction and Walker sampling.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library (``paper_2106_12270_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``alias_oracle.c`` (plain single-threaded C, compiled
+with gcc); this module only marshals numpy arrays.  ``exact.py`` holds the
+exact-rational definitions used to pin the C code on small inputs.
+
+Paper: Lehmann, Huebschle-Schneider & Sanders, "Weighted Random Sampling on
+GPUs", arXiv 2106.12270.  Section citations are in the C source.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_u64 = C.c_uint64
+_u32 = C.c_uint32
+_ptr = C.c_void_p
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "invalid weights", -5: "out of memory"}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.oracle_total.argtypes = [_ptr, _u64, _ptr]
+        L.oracle_total.restype = C.c_int
+        L.oracle_partition.argtypes = [_ptr, _u64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr]
+        L.oracle_partition.restype = None
+        L.oracle_prefix.argtypes = [_ptr, _u64, _ptr, _ptr]
+        L.oracle_prefix.restype = None
+        for fn in (L.oracle_split, L.oracle_split_linear):
+            fn.argtypes = [_ptr, _ptr, _ptr, _ptr, _u64, _u64, _ptr, _ptr, _u64, _ptr, _ptr,
+                           _ptr, _ptr]
+        L.oracle_split.restype = None
+        L.oracle_split_linear.restype = C.c_int
+        L.oracle_psa_build.argtypes = [_ptr, _u64, _u64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr,
+                                       _ptr, _ptr]
+        L.oracle_psa_build.restype = C.c_int
+        L.oracle_vose_build.argtypes = [_ptr, _u64, _ptr, _ptr]
+        L.oracle_vose_build.restype = C.c_int
+        L.oracle_philox4x32_10.argtypes = [_ptr, _ptr, _ptr]
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_sample.argtypes = [_ptr, _ptr, _u64, _u64, _u64, _u64, _u32, _ptr]
+        L.oracle_sample.restype = None
+        L.oracle_mass.argtypes = [_ptr, _ptr, _u64, _ptr, _ptr]
+        L.oracle_mass.restype = C.c_int
+        L.oracle_check.argtypes = [_ptr, _u64, _ptr, _ptr, _ptr, _ptr]
+        L.oracle_check.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _raise(st, what):
+    if st != 0:
+        raise OracleError(f"{what}: {STATUS.get(st, st)}")
+
+
+def total(w):
+    """(W_hi, W_lo, avg_hi, avg_lo); raises OracleError on invalid input."""
+    w = _f64(w)
+    out = np.zeros(4)
+    _raise(lib().oracle_total(_p(w), w.size, _p(out)), "total")
+    return out
+
+
+def partition(w, avg2):
+    w = _f64(w)
+    n = w.size
+    avg2 = _f64(avg2)
+    l_idx = np.empty(n, np.uint32)
+    h_idx = np.empty(n, np.uint32)
+    l_w = np.empty(n)
+    h_w = np.empty(n)
+    cnt = np.zeros(2, np.uint64)
+    lib().oracle_partition(_p(w), n, _p(avg2), _p(l_idx), _p(l_w), _p(h_idx), _p(h_w),
+                           _p(cnt))
+    L, H = int(cnt[0]), int(cnt[1])
+    return l_idx[:L].copy(), l_w[:L].copy(), h_idx[:H].copy(), h_w[:H].copy()
+
+
+def prefix(x):
+    """sigma[0..k] as (hi, lo) arrays, sigma[0] = 0."""
+    x = _f64(x)
+    hi = np.empty(x.size + 1)
+    lo = np.empty(x.size + 1)
+    lib().oracle_prefix(_p(x), x.size, _p(hi), _p(lo))
+    return hi, lo
+
+
+def split(sig_l, sig_h, avg2, ms, method="binary"):
+    """Split state (i, j, spill_hi, spill_lo) after m rows for each m in ms."""
+    lh, ll = (_f64(a) for a in sig_l)
+    hh, hl = (_f64(a) for a in sig_h)
+    L, H = lh.size - 1, hh.size - 1
+    ms = np.ascontiguousarray(ms, dtype=np.uint64)
+    k = ms.size
+    oi = np.empty(k, np.uint64)
+    oj = np.empty(k, np.uint64)
+    sh = np.empty(k)
+    sl = np.empty(k)
+    avg2 = _f64(avg2)
+    fn = lib().oracle_split if method == "binary" else lib().oracle_split_linear
+    r = fn(_p(lh), _p(ll), _p(hh), _p(hl), L, H, _p(avg2), _p(ms), k, _p(oi), _p(oj), _p(sh),
+           _p(sl))
+    out = (oi, oj, sh, sl)
+    if method != "binary":
+        return out + (bool(r),)
+    return out
+
+
+def psa_build(w, chunk=None, with_splits=False):
+    """Sequential PSA construction with sections of `chunk` rows (default: one
+    section = the plain sweep).  Returns (prob, alias[, info])."""
+    w = _f64(w)
+    n = w.size
+    chunk = n if chunk is None else int(chunk)
+    prob = np.empty(n)
+    alias = np.empty(n, np.uint32)
+    s = (n + chunk - 1) // chunk
+    si = np.empty(s + 1, np.uint64)
+    sj = np.empty(s + 1, np.uint64)
+    sph = np.empty(s + 1)
+    spl = np.empty(s + 1)
+    cnt = np.zeros(2, np.uint64)
+    avg = np.zeros(2)
+    st = lib().oracle_psa_build(_p(w), n, chunk, _p(prob), _p(alias), _p(si), _p(sj), _p(sph),
+                                _p(spl), _p(cnt), _p(avg))
+    _raise(st, "psa_build")
+    if with_splits:
+        info = dict(split_i=si, split_j=sj, spill_hi=sph, spill_lo=spl, L=int(cnt[0]),
+                    H=int(cnt[1]), avg=avg)
+        return prob, alias, info
+    return prob, alias
+
+
+def vose_build(w):
+    w = _f64(w)
+    n = w.size
+    prob = np.empty(n)
+    alias = np.empty(n, np.uint32)
+    _raise(lib().oracle_vose_build(_p(w), n, _p(prob), _p(alias)), "vose_build")
+    return prob, alias
+
+
+def philox(ctr, key):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().oracle_philox4x32_10(_p(ctr), _p(key), _p(out))
+    return out
+
+
+def sample(prob, alias, count, seed, first=0, table=0):
+    prob = _f64(prob)
+    alias = np.ascontiguousarray(alias, dtype=np.uint32)
+    out = np.empty(int(count), np.uint32)
+    lib().oracle_sample(_p(prob), _p(alias), prob.size, int(count), int(seed), int(first),
+                        int(table), _p(out))
+    return out
+
+
+def mass(prob, alias):
+    prob = _f64(prob)
+    alias = np.ascontiguousarray(alias, dtype=np.uint32)
+    hi = np.empty(prob.size)
+    lo = np.empty(prob.size)
+    _raise(lib().oracle_mass(_p(prob), _p(alias), prob.size, _p(hi), _p(lo)), "mass")
+    return hi, lo
+
+
+def check(w, prob, alias):
+    """Mass invariant of a table: dict(max_rel, sum_dev, zero_violations)."""
+    w = _f64(w)
+    prob = _f64(prob)
+    alias = np.ascontiguousarray(alias, dtype=np.uint32)
+    out = np.zeros(2)
+    zv = np.zeros(1, np.uint64)
+    _raise(lib().oracle_check(_p(w), w.size, _p(prob), _p(alias), _p(out), _p(zv)), "check")
+    return dict(max_rel=float(out[0]), sum_dev=float(out[1]), zero_violations=int(zv[0]))
+
+
+def chi2_gof(counts, expected, min_expected=5.0):
+    """Grouped chi-squared goodness of fit.  Bins are sorted by expected count
+    and adjacent bins merged until each expects >= min_expected draws.
+    Returns (statistic, dof, p_value)."""
+    from scipy.stats import chi2 as _chi2
+
+    counts = np.asarray(counts, dtype=np.float64)
+    expected = np.asarray(expected, dtype=np.float64)
+    order = np.argsort(expected, kind="stable")
+    c = counts[order]
+    e = expected[order]
+    gc, ge = [], []
+    acc_c = acc_e = 0.0
+    for ci, ei in zip(c, e):
+        acc_c += ci
+        acc_e += ei
+        if acc_e >= min_expected:
+            gc.append(acc_c)
+            ge.append(acc_e)
+            acc_c = acc_e = 0.0
+    if acc_e > 0:
+        if ge:
+            gc[-1] += acc_c
+            ge[-1] += acc_e
+        else:
+            gc.append(acc_c)
+            ge.append(acc_e)
+    gc = np.array(gc)
+    ge = np.array(ge)
+    stat = float(((gc - ge) ** 2 / ge).sum())
+    dof = max(len(ge) - 1, 1)
+    return stat, dof, float(_chi2.sf(stat, dof))

@@ -1,0 +1,610 @@
+/*
+ * CPU oracle for alias-table construction and sampling.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code with the HIP implementation.
+ *
+ * Plain, single-threaded, slow on purpose.  Every function follows a passage
+ * of Lehmann, Huebschle-Schneider & Sanders, "Weighted Random Sampling on
+ * GPUs" (arXiv 2106.12270), cited by section:
+ *
+ *   - problem statement (Sec. 1): items with weights w_i >= 0, W = sum w_i,
+ *     P(i) = w_i / W, sampling with replacement;
+ *   - alias table and Walker's O(1) draw (Sec. 2.2, "Alias Tables");
+ *   - light/heavy threshold W/N and Vose's O(N) construction (Sec. 2.2,
+ *     "Sequential Construction");
+ *   - PSA: split at s positions by binary search on light/heavy prefix sums,
+ *     spill, independent per-section packing (Sec. 2.2, "Parallel
+ *     Construction"; Sec. 4.1 split; Sec. 4.2 pack, whose loop body is the
+ *     sequential sweep "if w <= W/N ... else ...");
+ *   - baseline sampling, one draw per thread (Sec. 5).
+ *
+ * Arithmetic.  Weights, probabilities and the table are IEEE binary64.  The
+ * total W, the average W/N, all prefix sums, spills and the running residual
+ * are double-double (an unevaluated sum hi+lo of two doubles, ~106 bits),
+ * because the paper only fixes the 64-bit type and plain binary64 sums lose
+ * the 1e-12 per-item mass bound at the table sizes used.  Compile with
+ * -ffp-contract=off; fma() is called explicitly where an exact product is
+ * needed.
+ *
+ * Functions without a closed-form or brute-force pin are marked
+ * "parity unpinned" in their comment; every other function is pinned by a
+ * CPU test (exact rationals, closed forms, brute force, an independent
+ * Philox implementation, or statistics).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_EWEIGHTS (-2)
+#define OR_ENOMEM (-5)
+
+/* ------------------------------------------------------------------------ */
+/* Double-double arithmetic (Knuth TwoSum, Dekker FastTwoSum / TwoProduct,   */
+/* the accurate addition of Hida, Li & Bailey's QD library).                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double hi, lo;
+} dd;
+
+static dd two_sum(double a, double b) {
+  dd r;
+  double s = a + b;
+  double bb = s - a;
+  r.hi = s;
+  r.lo = (a - (s - bb)) + (b - bb);
+  return r;
+}
+
+/* requires |a| >= |b| or a == 0 */
+static dd fast_two_sum(double a, double b) {
+  dd r;
+  double s = a + b;
+  r.hi = s;
+  r.lo = b - (s - a);
+  return r;
+}
+
+static dd two_prod(double a, double b) {
+  dd r;
+  double p = a * b;
+  r.hi = p;
+  r.lo = fma(a, b, -p);
+  return r;
+}
+
+static dd dd_from(double a) {
+  dd r = {a, 0.0};
+  return r;
+}
+
+static dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+static dd dd_neg(dd a) {
+  dd r = {-a.hi, -a.lo};
+  return r;
+}
+
+static dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+
+static dd dd_add_d(dd a, double b) {
+  dd s = two_sum(a.hi, b);
+  s.lo += a.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+static dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return fast_two_sum(p.hi, p.lo);
+}
+
+static dd dd_div_d(dd a, double b) {
+  double q1 = a.hi / b;
+  dd p = two_prod(q1, b);
+  dd s = two_sum(a.hi, -p.hi);
+  s.lo -= p.lo;
+  s.lo += a.lo;
+  double q2 = (s.hi + s.lo) / b;
+  return fast_two_sum(q1, q2);
+}
+
+/* dd / dd -> dd (three-step long division) */
+static dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul_d(b, q1));
+  double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul_d(b, q2));
+  double q3 = r.hi / b.hi;
+  dd q = fast_two_sum(q1, q2);
+  return dd_add_d(q, q3);
+}
+
+/* a <= b for normalised dd values */
+static int dd_le(dd a, dd b) { return a.hi < b.hi || (a.hi == b.hi && a.lo <= b.lo); }
+
+/* Quotient a/b rounded to one binary64: one long-division step then a single
+ * rounding of q1 + q2.  For a, b exactly representable as doubles this is the
+ * correctly rounded IEEE quotient. */
+static double dd_quot_to_double(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul_d(b, q1));
+  double q2 = r.hi / b.hi;
+  return q1 + q2;
+}
+
+static double clamp01(double x) {
+  if (x < 0.0) return 0.0;
+  if (x > 1.0) return 1.0;
+  return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 1: validation, total weight W and average W/N (Sec. 1; Sec. 2.2).     */
+/* out4 = {W.hi, W.lo, avg.hi, avg.lo}.                                       */
+/* Weights must be finite and >= 0 with W > 0 (the paper allows any real     */
+/* weight; negative or non-finite weights define no distribution).            */
+/* ------------------------------------------------------------------------ */
+int oracle_total(const double *w, uint64_t n, double *out4) {
+  if (!w || !out4 || n == 0 || n > 0xFFFFFFFFull) return OR_EINVAL;
+  dd W = dd_from(0.0);
+  for (uint64_t i = 0; i < n; ++i) {
+    double x = w[i];
+    if (!(x >= 0.0) || !isfinite(x)) return OR_EWEIGHTS;
+    W = dd_add_d(W, x);
+  }
+  if (!(W.hi > 0.0) || !isfinite(W.hi)) return OR_EWEIGHTS;
+  dd avg = dd_div_d(W, (double)n);
+  out4[0] = W.hi;
+  out4[1] = W.lo;
+  out4[2] = avg.hi;
+  out4[3] = avg.lo;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: partition into light (w <= W/N) and heavy (w > W/N) items, each    */
+/* list in ascending item order, each entry carrying its weight (Sec. 2.2    */
+/* threshold; Sec. 4.2 "Weight in l and h Arrays"; Sec. 4.2 footnote remark  */
+/* that l and h are sorted by item index).  counts = {|L|, |H|}.             */
+/* ------------------------------------------------------------------------ */
+void oracle_partition(const double *w, uint64_t n, const double *avg2, uint32_t *l_idx,
+                      double *l_w, uint32_t *h_idx, double *h_w, uint64_t *counts) {
+  dd avg = {avg2[0], avg2[1]};
+  uint64_t L = 0, H = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (dd_le(dd_from(w[i]), avg)) {
+      l_idx[L] = (uint32_t)i;
+      l_w[L] = w[i];
+      ++L;
+    } else {
+      h_idx[H] = (uint32_t)i;
+      h_w[H] = w[i];
+      ++H;
+    }
+  }
+  counts[0] = L;
+  counts[1] = H;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 3: inclusive-from-zero prefix sums sigma[0..k] (sigma[0] = 0), in dd  */
+/* (Sec. 2.2, "prefix sums of light and heavy items").                       */
+/* ------------------------------------------------------------------------ */
+void oracle_prefix(const double *x, uint64_t k, double *s_hi, double *s_lo) {
+  dd s = dd_from(0.0);
+  s_hi[0] = 0.0;
+  s_lo[0] = 0.0;
+  for (uint64_t t = 0; t < k; ++t) {
+    s = dd_add_d(s, x[t]);
+    s_hi[t + 1] = s.hi;
+    s_lo[t + 1] = s.lo;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 4: split (Sec. 2.2 "Parallel Construction"; Sec. 4.1 baseline).      */
+/*                                                                          */
+/* After m rows the sequential sweep has used i lights and closed j heavies  */
+/* (i + j = m).  With f(j) = sigma_l[m-j] + sigma_h[j], f is strictly        */
+/* increasing in j (each heavy weighs more than each light) and the sweep's */
+/* j is the largest j in [max(0, m-|L|), min(m, |H|)] with f(j) <= m*avg.   */
+/* The spill is the residual weight of the current heavy,                    */
+/* sigma_l[i] + sigma_h[j+1] - m*avg (0 when no heavy is left).             */
+/* ------------------------------------------------------------------------ */
+static dd sig(const double *hi, const double *lo, uint64_t k) {
+  dd r = {hi[k], lo[k]};
+  return r;
+}
+
+static int split_pred(const double *slh, const double *sll, const double *shh, const double *shl,
+                      uint64_t m, uint64_t j, dd mavg) {
+  dd f = dd_add(sig(slh, sll, m - j), sig(shh, shl, j));
+  return dd_le(f, mavg);
+}
+
+static void split_spill(const double *slh, const double *sll, const double *shh, const double *shl,
+                        uint64_t H, uint64_t i, uint64_t j, dd mavg, double *sp_hi,
+                        double *sp_lo) {
+  if (j < H) {
+    dd r = dd_sub(dd_add(sig(slh, sll, i), sig(shh, shl, j + 1)), mavg);
+    *sp_hi = r.hi;
+    *sp_lo = r.lo;
+  } else {
+    *sp_hi = 0.0;
+    *sp_lo = 0.0;
+  }
+}
+
+/* binary search (the paper's baseline split) */
+void oracle_split(const double *slh, const double *sll, const double *shh, const double *shl,
+                  uint64_t L, uint64_t H, const double *avg2, const uint64_t *ms, uint64_t count,
+                  uint64_t *out_i, uint64_t *out_j, double *sp_hi, double *sp_lo) {
+  dd avg = {avg2[0], avg2[1]};
+  for (uint64_t k = 0; k < count; ++k) {
+    uint64_t m = ms[k];
+    dd mavg = dd_mul_d(avg, (double)m);
+    uint64_t lo = (m > L) ? m - L : 0;     /* predicate true at lo */
+    uint64_t hi = (m < H) ? m : H;         /* answer <= hi */
+    while (lo < hi) {                      /* largest j with pred(j) */
+      uint64_t mid = lo + (hi - lo + 1) / 2;
+      if (split_pred(slh, sll, shh, shl, m, mid, mavg))
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    out_i[k] = m - lo;
+    out_j[k] = lo;
+    split_spill(slh, sll, shh, shl, H, m - lo, lo, mavg, &sp_hi[k], &sp_lo[k]);
+  }
+}
+
+/* brute force: scan every admissible j; also reports whether f was strictly
+ * increasing on the scanned range (returns 0 if so, 1 otherwise) */
+int oracle_split_linear(const double *slh, const double *sll, const double *shh,
+                        const double *shl, uint64_t L, uint64_t H, const double *avg2,
+                        const uint64_t *ms, uint64_t count, uint64_t *out_i, uint64_t *out_j,
+                        double *sp_hi, double *sp_lo) {
+  dd avg = {avg2[0], avg2[1]};
+  int nonmono = 0;
+  for (uint64_t k = 0; k < count; ++k) {
+    uint64_t m = ms[k];
+    dd mavg = dd_mul_d(avg, (double)m);
+    uint64_t jmin = (m > L) ? m - L : 0;
+    uint64_t jmax = (m < H) ? m : H;
+    uint64_t best = jmin;
+    dd prev = {-INFINITY, 0.0};
+    for (uint64_t j = jmin; j <= jmax; ++j) {
+      dd f = dd_add(sig(slh, sll, m - j), sig(shh, shl, j));
+      if (j > jmin && dd_le(f, prev)) nonmono = 1;
+      prev = f;
+      if (dd_le(f, mavg)) best = j;
+    }
+    out_i[k] = m - best;
+    out_j[k] = best;
+    split_spill(slh, sll, shh, shl, H, m - best, best, mavg, &sp_hi[k], &sp_lo[k]);
+  }
+  return nonmono;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 5: pack one section (Sec. 2.2; Sec. 4.2 chunked pack loop            */
+/* "if w <= W/N then ... else ...").                                         */
+/*                                                                          */
+/* State (i, j, r): next light, current heavy, residual weight r of heavy j. */
+/* While the section is not done:                                           */
+/*   - if heavy j belongs to the section and (r <= avg or the section's     */
+/*     lights are used up): heavy j fills its own row: prob = r/avg, alias  */
+/*     = next heavy (itself if it is the last); the next heavy's residual   */
+/*     becomes w_next - (avg - r);                                           */
+/*   - otherwise light i fills its row from heavy j: prob = w_i/avg, alias  */
+/*     = heavy j (itself if no heavy is left), and r drops by avg - w_i.    */
+/* The section bounds, taken from the split, are authoritative.             */
+/* ------------------------------------------------------------------------ */
+static void pack_section(const uint32_t *l_idx, const double *l_w, const uint32_t *h_idx,
+                         const double *h_w, uint64_t H, dd avg, uint64_t i, uint64_t j, dd r,
+                         uint64_t i_end, uint64_t j_end, double *prob, uint32_t *alias) {
+  while (i < i_end || j < j_end) {
+    if (j < j_end && (dd_le(r, avg) || i == i_end)) {
+      uint32_t h = h_idx[j];
+      prob[h] = clamp01(dd_quot_to_double(r, avg));
+      if (j + 1 < H) {
+        alias[h] = h_idx[j + 1];
+        r = dd_add(dd_sub(r, avg), dd_from(h_w[j + 1]));
+      } else {
+        alias[h] = h;
+      }
+      ++j;
+    } else {
+      uint32_t l = l_idx[i];
+      prob[l] = clamp01(dd_quot_to_double(dd_from(l_w[i]), avg));
+      alias[l] = (j < H) ? h_idx[j] : l;
+      if (j < H) r = dd_sub(r, dd_sub(avg, dd_from(l_w[i])));
+      ++i;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole PSA construction with sections of `chunk` rows:                     */
+/* m_k = min(k*chunk, n) for k = 0..s, s = ceil(n/chunk).                   */
+/* chunk >= n gives the plain sequential sweep.  Optional outputs (may be   */
+/* NULL): split_i/split_j/spill_hi/spill_lo of length s+1; counts = {L, H}. */
+/* ------------------------------------------------------------------------ */
+int oracle_psa_build(const double *w, uint64_t n, uint64_t chunk, double *prob, uint32_t *alias,
+                     uint64_t *split_i, uint64_t *split_j, double *spill_hi, double *spill_lo,
+                     uint64_t *counts, double *avg_out) {
+  if (chunk == 0) return OR_EINVAL;
+  double tot[4];
+  int st = oracle_total(w, n, tot);
+  if (st) return st;
+  dd avg = {tot[2], tot[3]};
+  if (avg_out) {
+    avg_out[0] = tot[2];
+    avg_out[1] = tot[3];
+  }
+  uint32_t *l_idx = malloc(n * sizeof(uint32_t)), *h_idx = malloc(n * sizeof(uint32_t));
+  double *l_w = malloc(n * sizeof(double)), *h_w = malloc(n * sizeof(double));
+  uint64_t cnt[2];
+  int rc = OR_ENOMEM;
+  double *slh = NULL, *sll = NULL, *shh = NULL, *shl = NULL;
+  uint64_t *ms = NULL, *si = NULL, *sj = NULL;
+  double *sph = NULL, *spl = NULL;
+  if (!l_idx || !h_idx || !l_w || !h_w) goto out;
+  oracle_partition(w, n, tot + 2, l_idx, l_w, h_idx, h_w, cnt);
+  uint64_t L = cnt[0], H = cnt[1];
+  if (counts) {
+    counts[0] = L;
+    counts[1] = H;
+  }
+  slh = malloc((L + 1) * sizeof(double));
+  sll = malloc((L + 1) * sizeof(double));
+  shh = malloc((H + 1) * sizeof(double));
+  shl = malloc((H + 1) * sizeof(double));
+  uint64_t s = (n + chunk - 1) / chunk;
+  ms = malloc((s + 1) * sizeof(uint64_t));
+  si = malloc((s + 1) * sizeof(uint64_t));
+  sj = malloc((s + 1) * sizeof(uint64_t));
+  sph = malloc((s + 1) * sizeof(double));
+  spl = malloc((s + 1) * sizeof(double));
+  if (!slh || !sll || !shh || !shl || !ms || !si || !sj || !sph || !spl) goto out;
+  oracle_prefix(l_w, L, slh, sll);
+  oracle_prefix(h_w, H, shh, shl);
+  for (uint64_t k = 0; k <= s; ++k) ms[k] = (k * chunk < n) ? k * chunk : n;
+  oracle_split(slh, sll, shh, shl, L, H, tot + 2, ms, s + 1, si, sj, sph, spl);
+  for (uint64_t k = 0; k < s; ++k) {
+    dd r = {sph[k], spl[k]};
+    pack_section(l_idx, l_w, h_idx, h_w, H, avg, si[k], sj[k], r, si[k + 1], sj[k + 1], prob,
+                 alias);
+  }
+  if (split_i)
+    for (uint64_t k = 0; k <= s; ++k) {
+      split_i[k] = si[k];
+      split_j[k] = sj[k];
+      spill_hi[k] = sph[k];
+      spill_lo[k] = spl[k];
+    }
+  rc = OR_OK;
+out:
+  free(l_idx);
+  free(h_idx);
+  free(l_w);
+  free(h_w);
+  free(slh);
+  free(sll);
+  free(shh);
+  free(shl);
+  free(ms);
+  free(si);
+  free(sj);
+  free(sph);
+  free(spl);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Vose's sequential construction (Sec. 2.2 "Sequential Construction").      */
+/* Bucket-unit weights p_i = w_i/avg in dd; worklists of small (p <= 1) and */
+/* large (p > 1) items, filled in index order and used last-in-first-out;   */
+/* a large item's remainder p_g + p_l - 1 sends it back to the small list   */
+/* once it is <= 1.  Items left over get prob 1, alias self.                */
+/* Used as a second, structurally different construction: its tables are   */
+/* compared by the mass invariant only.                                      */
+/* ------------------------------------------------------------------------ */
+int oracle_vose_build(const double *w, uint64_t n, double *prob, uint32_t *alias) {
+  double tot[4];
+  int st = oracle_total(w, n, tot);
+  if (st) return st;
+  dd avg = {tot[2], tot[3]};
+  dd one = dd_from(1.0);
+  double *ph = malloc(n * sizeof(double)), *pl = malloc(n * sizeof(double));
+  uint32_t *small = malloc(n * sizeof(uint32_t)), *large = malloc(n * sizeof(uint32_t));
+  if (!ph || !pl || !small || !large) {
+    free(ph);
+    free(pl);
+    free(small);
+    free(large);
+    return OR_ENOMEM;
+  }
+  uint64_t ns = 0, nl = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    dd p = dd_div(dd_from(w[i]), avg);
+    ph[i] = p.hi;
+    pl[i] = p.lo;
+    if (dd_le(p, one))
+      small[ns++] = (uint32_t)i;
+    else
+      large[nl++] = (uint32_t)i;
+  }
+  while (ns > 0 && nl > 0) {
+    uint32_t l = small[--ns];
+    uint32_t g = large[--nl];
+    dd p_l = {ph[l], pl[l]};
+    dd p_g = {ph[g], pl[g]};
+    prob[l] = clamp01(p_l.hi + p_l.lo);
+    alias[l] = g;
+    p_g = dd_sub(dd_add(p_g, p_l), one);
+    ph[g] = p_g.hi;
+    pl[g] = p_g.lo;
+    if (dd_le(p_g, one))
+      small[ns++] = g;
+    else
+      large[nl++] = g;
+  }
+  while (nl > 0) {
+    uint32_t g = large[--nl];
+    prob[g] = 1.0;
+    alias[g] = g;
+  }
+  while (ns > 0) {
+    uint32_t l = small[--ns];
+    prob[l] = 1.0;
+    alias[l] = l;
+  }
+  free(ph);
+  free(pl);
+  free(small);
+  free(large);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): 10 rounds of two 32x32->64 multiplies by       */
+/* 0xD2511F53 and 0xCD9E8D57 with a Weyl key schedule (+0x9E3779B9,         */
+/* +0xBB67AE85).  Pinned against the rocRAND engine in a CPU test.          */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Walker sampling (Sec. 2.2; Sec. 5 baseline): one Philox block per draw.   */
+/* Draw t of table `table`: counter (lo32 t, hi32 t, table, 0), key (lo32   */
+/* seed, hi32 seed).  Row k = floor(x * n / 2^64) with x = r0 + 2^32 r1;    */
+/* coin u = (r2 + 2^32 r3) >> 11 (53 bits); output k if u * 2^-53 <        */
+/* prob[k], else alias[k].  All integer or exact, so any correct            */
+/* implementation reproduces it bit for bit.                                 */
+/* ------------------------------------------------------------------------ */
+void oracle_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
+                   uint64_t seed, uint64_t first, uint32_t table, uint32_t *out) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (uint64_t q = 0; q < count; ++q) {
+    uint64_t t = first + q;
+    uint32_t ctr[4] = {(uint32_t)t, (uint32_t)(t >> 32), table, 0u};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    uint64_t x = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
+    uint64_t k = (uint64_t)(((unsigned __int128)x * n) >> 64);
+    uint64_t u = ((uint64_t)r[2] | ((uint64_t)r[3] << 32)) >> 11;
+    out[q] = ((double)u * 0x1p-53 < prob[k]) ? (uint32_t)k : alias[k];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Checker (Sec. 2.2: each row is a bucket of W/N; row k gives prob[k] of a */
+/* bucket to item k and the rest to alias[k]).  Per-item reconstructed mass */
+/* in buckets, accumulated in dd: mass_i = sum_k [k=i] prob[k] +            */
+/* sum_k [alias[k]=i] (1 - prob[k]).  Returns OR_EINVAL if any alias is out */
+/* of range or any prob is outside [0,1].                                   */
+/* ------------------------------------------------------------------------ */
+int oracle_mass(const double *prob, const uint32_t *alias, uint64_t n, double *m_hi,
+                double *m_lo) {
+  for (uint64_t i = 0; i < n; ++i) {
+    m_hi[i] = 0.0;
+    m_lo[i] = 0.0;
+  }
+  for (uint64_t k = 0; k < n; ++k) {
+    double p = prob[k];
+    uint32_t a = alias[k];
+    if (!(p >= 0.0 && p <= 1.0) || a >= n) return OR_EINVAL;
+    dd own = {m_hi[k], m_lo[k]};
+    own = dd_add_d(own, p);
+    m_hi[k] = own.hi;
+    m_lo[k] = own.lo;
+    dd rest = two_sum(1.0, -p);
+    dd al = {m_hi[a], m_lo[a]};
+    al = dd_add(al, rest);
+    m_hi[a] = al.hi;
+    m_lo[a] = al.lo;
+  }
+  return OR_OK;
+}
+
+/* Expected mass n*w_i/W = w_i/avg (dd) and the per-item relative error of a
+ * table.  Reports max relative error over w_i > 0, the number of items with
+ * w_i == 0 but nonzero mass, and |sum(mass) - n| / n.  Returns the
+ * oracle_mass status. */
+int oracle_check(const double *w, uint64_t n, const double *prob, const uint32_t *alias,
+                 double *out2, uint64_t *zero_violations) {
+  double tot[4];
+  int st = oracle_total(w, n, tot);
+  if (st) return st;
+  dd avg = {tot[2], tot[3]};
+  double *mh = malloc(n * sizeof(double)), *ml = malloc(n * sizeof(double));
+  if (!mh || !ml) {
+    free(mh);
+    free(ml);
+    return OR_ENOMEM;
+  }
+  st = oracle_mass(prob, alias, n, mh, ml);
+  if (st) {
+    free(mh);
+    free(ml);
+    return st;
+  }
+  double maxrel = 0.0;
+  uint64_t zv = 0;
+  dd total = dd_from(0.0);
+  for (uint64_t i = 0; i < n; ++i) {
+    dd m = {mh[i], ml[i]};
+    total = dd_add(total, m);
+    if (w[i] == 0.0) {
+      if (m.hi != 0.0 || m.lo != 0.0) ++zv;
+      continue;
+    }
+    dd e = dd_div(dd_from(w[i]), avg);
+    dd d = dd_sub(m, e);
+    double rel = fabs(d.hi + d.lo) / (e.hi + e.lo);
+    if (rel > maxrel) maxrel = rel;
+  }
+  dd dev = dd_sub(total, dd_from((double)n));
+  out2[0] = maxrel;
+  out2[1] = fabs(dev.hi + dev.lo) / (double)n;
+  *zero_violations = zv;
+  free(mh);
+  free(ml);
+  return OR_OK;
+}

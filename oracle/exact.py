@@ -1,0 +1,120 @@
+"""Exact-rational definitions (pure Python ``fractions``), for small inputs.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  These are the plain
+definitions the C oracle approximates in double-double arithmetic; tests use
+them to pin the C code.  Paper: arXiv 2106.12270.
+"""
+from fractions import Fraction
+
+
+def _fr(x):
+    return x if isinstance(x, Fraction) else Fraction(x)
+
+
+def average(w):
+    """W/N (Sec. 1 total weight; Sec. 2.2 bucket size W/N)."""
+    w = [_fr(x) for x in w]
+    return sum(w, Fraction(0)) / len(w)
+
+
+def partition(w):
+    """Light iff w_i <= W/N, else heavy; both lists in item order (Sec. 2.2)."""
+    avg = average(w)
+    L = [i for i, x in enumerate(w) if _fr(x) <= avg]
+    H = [i for i, x in enumerate(w) if _fr(x) > avg]
+    return L, H, avg
+
+
+def sweep(w):
+    """The sequential sweep in exact arithmetic (Sec. 2.2 parallel construction
+    with one section; Sec. 4.2 pack loop): returns exact row weights in
+    buckets (prob) and aliases.  Also returns the state (i, j, r) after every
+    row, for checking splits."""
+    w = [_fr(x) for x in w]
+    n = len(w)
+    L, H, avg = partition(w)
+    prob = [None] * n
+    alias = [None] * n
+    states = []
+    i = j = 0
+    r = w[H[0]] if H else Fraction(0)
+    states.append((0, 0, r if H else Fraction(0)))
+    while i < len(L) or j < len(H):
+        if j < len(H) and (r <= avg or i == len(L)):
+            h = H[j]
+            prob[h] = r / avg
+            if j + 1 < len(H):
+                alias[h] = H[j + 1]
+                r = r - avg + w[H[j + 1]]
+            else:
+                alias[h] = h
+                r = Fraction(0)
+            j += 1
+        else:
+            l = L[i]
+            prob[l] = w[l] / avg
+            if j < len(H):
+                alias[l] = H[j]
+                r = r - (avg - w[l])
+            else:
+                alias[l] = l
+            i += 1
+        states.append((i, j, r))
+    return prob, alias, states
+
+
+def split(w, m):
+    """Split state after m rows by the prefix-sum rule (Sec. 2.2): the largest
+    j in [max(0, m-|L|), min(m, |H|)] with sigma_l[m-j] + sigma_h[j] <= m*avg,
+    found by scanning every j; spill = sigma_l[i] + sigma_h[j+1] - m*avg."""
+    w = [_fr(x) for x in w]
+    L, H, avg = partition(w)
+    sl = [Fraction(0)]
+    for t in L:
+        sl.append(sl[-1] + w[t])
+    sh = [Fraction(0)]
+    for t in H:
+        sh.append(sh[-1] + w[t])
+    best = None
+    for j in range(max(0, m - len(L)), min(m, len(H)) + 1):
+        if sl[m - j] + sh[j] <= m * avg:
+            best = j
+    if best is None:
+        best = max(0, m - len(L))
+    i = m - best
+    spill = sl[i] + sh[best + 1] - m * avg if best < len(H) else Fraction(0)
+    return i, best, spill
+
+
+def mass(prob, alias):
+    """Per-item mass in buckets: own-row share plus the alias shares (Sec. 2.2)."""
+    n = len(prob)
+    m = [Fraction(0)] * n
+    for k in range(n):
+        p = _fr(prob[k])
+        m[k] += p
+        m[alias[k]] += 1 - p
+    return m
+
+
+def sampler_distribution(prob, alias):
+    """Exact output distribution of the integer Walker map used for sampling:
+    row k = floor(x*n/2^64) for a uniform 64-bit x, coin u uniform on
+    [0, 2^53), output k iff u*2^-53 < prob[k] else alias[k]."""
+    n = len(prob)
+    two64 = 1 << 64
+
+    def ceil_div(a, b):
+        return -((-a) // b)
+
+    out = [Fraction(0)] * n
+    for k in range(n):
+        rows = ceil_div((k + 1) * two64, n) - ceil_div(k * two64, n)
+        p_row = Fraction(rows, two64)
+        # number of u in [0, 2^53) with u < prob*2^53
+        thr = _fr(prob[k]) * (1 << 53)
+        keep = min(max(ceil_div(thr.numerator, thr.denominator), 0), 1 << 53)
+        p_keep = Fraction(keep, 1 << 53)
+        out[k] += p_row * p_keep
+        out[alias[k]] += p_row * (1 - p_keep)
+    return out

@@ -1,0 +1,149 @@
+"""Seeded synthetic inputs (host, numpy PCG64).
+
+This module only draws weights and table sizes; it holds none of the alias
+method's arithmetic and is shared by the tests, the benchmark and the oracle
+checks.  The paper evaluates on uniform random weights and on a shuffled power
+law w_i = i^-alpha (arXiv 2106.12270, Sec. 6); the workloads below use those
+plus lognormal weights and batches of tables of log-uniform sizes.
+"""
+import numpy as np
+
+# Fixed seeds per workload: weights 0x5EED0000 + k, sampling 0xA11A5.
+SAMPLE_SEED = 0xA11A5
+
+
+def weight_seed(k: int) -> int:
+    return 0x5EED0000 + k
+
+
+def uniform01(n: int, seed: int) -> np.ndarray:
+    """w = 1 - U with U uniform on [0, 1) at 53-bit resolution, so w in (0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return 1.0 - rng.random(n)
+
+
+def power_law(n: int, alpha: float, seed: int) -> np.ndarray:
+    """Shuffled power law: w_i = (i+1)^-alpha for i = 0..n-1, randomly permuted."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-float(alpha))
+    return w[rng.permutation(n)]
+
+
+def lognormal(n: int, sigma: float, seed: int, mu: float = 0.0) -> np.ndarray:
+    """w = exp(mu + sigma * Z), Z standard normal, i.i.d."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(mu + sigma * rng.standard_normal(n))
+
+
+def sorted_descending(w: np.ndarray) -> np.ndarray:
+    return np.sort(w)[::-1].copy()
+
+
+def exact_integers(n: int, seed: int, max_w: int = 1 << 20, zero_frac: float = 0.0) -> np.ndarray:
+    """Integer weights in [0, max_w] whose total is a multiple of n, so W/N is
+    an integer and every sum the construction forms is exact in binary64 while
+    n * max_w < 2^53.  A fraction `zero_frac` of the items is set to zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.integers(0, max_w + 1, size=n).astype(np.int64)
+    if zero_frac > 0:
+        w[rng.random(n) < zero_frac] = 0
+    rem = int(w.sum()) % n
+    if rem:
+        # raise some items (never above max_w) until the total is a multiple of n
+        need = n - rem
+        order = rng.permutation(n)
+        for i in order:
+            room = max_w - int(w[i])
+            take = min(room, need)
+            w[i] += take
+            need -= take
+            if need == 0:
+                break
+        if need:
+            # lower instead
+            need = rem
+            for i in order:
+                take = min(int(w[i]), need)
+                w[i] -= take
+                need -= take
+                if need == 0:
+                    break
+    if w.sum() == 0:
+        w[0] = n
+    return w.astype(np.float64)
+
+
+def log_uniform_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Table sizes n_t = floor(lo * (hi/lo)^U), U uniform on [0, 1), clamped to [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.random(count)
+    n = np.floor(lo * (hi / lo) ** u).astype(np.int64)
+    return np.clip(n, lo, hi)
+
+
+def offsets_from_sizes(sizes) -> np.ndarray:
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(np.asarray(sizes, dtype=np.uint64))
+    return off
+
+
+def apportion(total: int, sizes) -> np.ndarray:
+    """Split `total` draws over tables proportionally to their sizes by the
+    largest-remainder rule (the parts sum to `total` exactly)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    S = int(sizes.sum())
+    quota = [total * int(s) for s in sizes]          # exact integers, / S
+    base = np.array([q // S for q in quota], dtype=np.int64)
+    rem = np.array([q % S for q in quota], dtype=np.int64)
+    short = total - int(base.sum())
+    if short:
+        order = np.lexsort((np.arange(len(sizes)), -rem))
+        base[order[:short]] += 1
+    return base
+
+
+def batch_lognormal(sizes, seed: int, sigma: float = 1.0) -> np.ndarray:
+    """Concatenated lognormal(0, sigma) weights for a batch of tables."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.exp(sigma * rng.standard_normal(int(np.sum(sizes))))
+
+
+def batch_zipf(sizes, seed: int, exponents=(0.5, 1.0, 1.5)):
+    """Per table: exponent s drawn uniformly from `exponents`, w_i = (i+1)^-s,
+    randomly permuted.  Returns (weights, exponents per table)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ex = np.asarray(exponents, dtype=np.float64)
+    s_t = ex[rng.integers(0, len(ex), size=len(sizes))]
+    parts = []
+    for n, s in zip(sizes, s_t):
+        w = np.arange(1, int(n) + 1, dtype=np.float64) ** (-s)
+        parts.append(w[rng.permutation(int(n))])
+    return np.concatenate(parts), s_t
+
+
+# The workloads (sizes and distributions) used by tests and the benchmark.
+WORKLOADS = {
+    "uniform_2p20": dict(n=1 << 20, dist="uniform", draws=10 ** 7, chunk=1 << 10, key=1),
+    "powerlaw_2p27": dict(n=1 << 27, dist="powerlaw", alpha=1.0, draws=10 ** 9, chunk=1 << 10,
+                          key=2),
+    "lognormal_2p28": dict(n=1 << 28, dist="lognormal", sigma=2.0, draws=10 ** 9,
+                           chunk=1 << 10, key=3),
+    "batch_100k_16_65536": dict(tables=100_000, lo=16, hi=65536, dist="lognormal", sigma=1.0,
+                                draws=1 << 30, key=4),
+    "batch_1024_2p14_2p22": dict(tables=1024, lo=1 << 14, hi=1 << 22, dist="zipf",
+                                 draws=1 << 31, key=5),
+}
+
+
+def make_weights(name: str, n: int = None) -> np.ndarray:
+    """Weights of a single-table workload (optionally at a smaller n, same recipe)."""
+    cfg = WORKLOADS[name]
+    n = cfg["n"] if n is None else n
+    seed = weight_seed(cfg["key"])
+    if cfg["dist"] == "uniform":
+        return uniform01(n, seed)
+    if cfg["dist"] == "powerlaw":
+        return power_law(n, cfg["alpha"], seed)
+    if cfg["dist"] == "lognormal":
+        return lognormal(n, cfg["sigma"], seed)
+    raise KeyError(name)

@@ -1,0 +1,357 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+rational arithmetic (the plain definitions), closed forms, brute force, an
+independent Philox implementation (rocRAND's engine), and statistics.
+Paper: arXiv 2106.12270 (Sec. 2.2 alias tables, Vose, PSA; Sec. 5 sampling).
+"""
+import itertools
+import os
+import shutil
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from paper_2106_12270_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rn(fr):
+    """Correctly rounded binary64 value of a Fraction (Python's int/int
+    true division is correctly rounded)."""
+    return fr.numerator / fr.denominator
+
+
+# --------------------------------------------------------------------------
+# Closed forms (Sec. 2.2)
+# --------------------------------------------------------------------------
+def test_single_item(oracle):
+    prob, alias = oracle.psa_build(np.array([3.5]))
+    assert prob.tolist() == [1.0] and alias.tolist() == [0]
+
+
+def test_all_equal_weights_are_all_light(oracle):
+    for n in (2, 7, 1000):
+        prob, alias = oracle.psa_build(np.full(n, 0.37))
+        assert np.all(prob == 1.0)
+        assert np.array_equal(alias, np.arange(n, dtype=np.uint32))
+
+
+def test_two_items_one_three(oracle):
+    # avg = 2: item 0 light with 1/2 of a bucket, item 1 heavy fills the rest
+    prob, alias = oracle.psa_build(np.array([1.0, 3.0]))
+    assert prob.tolist() == [0.5, 1.0]
+    assert alias.tolist() == [1, 1]
+
+
+def test_one_heavy_many_equal_lights(oracle):
+    n = 64
+    w = np.ones(n)
+    w[17] = 1.0 + n  # W = 2n, avg = 2: each light holds half a bucket
+    prob, alias = oracle.psa_build(w)
+    m_hi, m_lo = oracle.mass(prob, alias)
+    m = m_hi + m_lo
+    assert np.all(m[np.arange(n) != 17] == 0.5)
+    assert m[17] == (n + 1) / 2
+    assert np.all(alias[np.arange(n) != 17] == 17)
+
+
+def test_zero_weight_items_get_no_mass(oracle):
+    w = inputs.exact_integers(4096, 11, zero_frac=0.3)
+    prob, alias = oracle.psa_build(w, chunk=64)
+    r = oracle.check(w, prob, alias)
+    assert r["zero_violations"] == 0
+    # sums are exact here; only each stored prob is rounded once
+    assert r["max_rel"] <= 1e-13
+    # a zero-weight item never wins its own row
+    assert np.all(prob[w == 0] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Exact rationals on small inputs: the C oracle equals the exact sweep
+# --------------------------------------------------------------------------
+SMALL_MULTISETS = [
+    (0, 2, 2, 4),          # a tie w = avg, a zero
+    (1, 1, 1, 1),          # all equal
+    (0, 0, 0, 4),          # one heavy takes everything
+    (3, 1, 2, 2),          # ties
+    (5, 0, 1),             # avg 2
+    (6, 0, 0, 2, 2),       # avg 2, ties and zeros
+    (9, 1, 1, 1),          # avg 3
+    (4, 4, 1, 1, 5),       # avg 3
+]
+
+
+@pytest.mark.parametrize("ms", SMALL_MULTISETS)
+def test_all_permutations_match_exact_sweep(oracle, ms):
+    n = len(ms)
+    for perm in set(itertools.permutations(ms)):
+        w = np.array(perm, dtype=np.float64)
+        ep, ea, _ = exact.sweep(list(perm))
+        for chunk in range(1, n + 1):
+            prob, alias = oracle.psa_build(w, chunk=chunk)
+            assert alias.tolist() == ea, (perm, chunk)
+            assert prob.tolist() == [rn(p) for p in ep], (perm, chunk)
+        em = exact.mass(ep, ea)
+        avg = exact.average(list(perm))
+        assert em == [Fraction(int(x)) / avg for x in perm]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exact_integer_inputs_match_exact_sweep(oracle, seed):
+    n = 37 + 11 * seed
+    w = inputs.exact_integers(n, 100 + seed, max_w=50, zero_frac=0.1)
+    ep, ea, states = exact.sweep([int(x) for x in w])
+    for chunk in (1, 2, 5, 16, n):
+        prob, alias, info = oracle.psa_build(w, chunk=chunk, with_splits=True)
+        assert alias.tolist() == ea
+        assert prob.tolist() == [rn(p) for p in ep]
+        # every split equals the exact sweep state after m rows
+        s = len(info["split_i"]) - 1
+        for k in range(s + 1):
+            m = min(k * chunk, n)
+            i, j, r = states[m]
+            assert (int(info["split_i"][k]), int(info["split_j"][k])) == (i, j)
+            sp = Fraction(info["spill_hi"][k]) + Fraction(info["spill_lo"][k])
+            assert sp == r
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_general_floats_small_masses_vs_exact(oracle, seed):
+    rng = np.random.default_rng(seed)
+    n = 50
+    w = rng.random(n) ** 3
+    w[rng.integers(0, n, 3)] = 0.0
+    prob, alias = oracle.psa_build(w, chunk=7)
+    fr_w = [Fraction(float(x)) for x in w]
+    avg = sum(fr_w) / n
+    m = exact.mass([Fraction(float(p)) for p in prob], alias.tolist())
+    for i in range(n):
+        e = fr_w[i] / avg
+        if e == 0:
+            assert m[i] == 0
+        else:
+            assert abs(m[i] - e) / e < Fraction(1, 10 ** 14)
+
+
+# --------------------------------------------------------------------------
+# Split: prefix-sum rule == brute force == the sweep's own state
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("gen", ["uniform", "powerlaw", "lognormal", "exact"])
+def test_split_binary_equals_brute_force(oracle, gen):
+    n = 3000
+    if gen == "uniform":
+        w = inputs.uniform01(n, 5)
+    elif gen == "powerlaw":
+        w = inputs.power_law(n, 1.0, 5)
+    elif gen == "lognormal":
+        w = inputs.lognormal(n, 2.0, 5)
+    else:
+        w = inputs.exact_integers(n, 5)
+    tot = oracle.total(w)
+    l_idx, l_w, h_idx, h_w = oracle.partition(w, tot[2:])
+    sl = oracle.prefix(l_w)
+    sh = oracle.prefix(h_w)
+    ms = np.arange(0, n + 1, dtype=np.uint64)
+    b = oracle.split(sl, sh, tot[2:], ms)
+    lin = oracle.split(sl, sh, tot[2:], ms, method="linear")
+    assert not lin[4], "f(j) must be strictly increasing"
+    for a, c in zip(b, lin[:4]):
+        assert np.array_equal(a, c)
+    # consecutive splits move by one row
+    di = np.diff(b[0].astype(np.int64))
+    dj = np.diff(b[1].astype(np.int64))
+    assert np.all(di + dj == 1) and np.all(di >= 0) and np.all(dj >= 0)
+    # spill lies in (0, w of the current heavy] while heavies remain
+    H = len(h_w)
+    for k in range(0, n + 1, 37):
+        j = int(b[1][k])
+        if j < H:
+            sp = b[2][k] + b[3][k]
+            assert 0 < sp <= h_w[j] * (1 + 1e-15)
+
+
+def test_partition_is_stable_and_threshold_exact(oracle):
+    w = inputs.exact_integers(1000, 9, max_w=8)  # many ties at w = avg
+    tot = oracle.total(w)
+    avg = tot[2] + tot[3]
+    l_idx, l_w, h_idx, h_w = oracle.partition(w, tot[2:])
+    assert np.all(np.diff(l_idx.astype(np.int64)) > 0)
+    assert np.all(np.diff(h_idx.astype(np.int64)) > 0)
+    assert np.all(w[l_idx] <= avg) and np.all(w[h_idx] > avg)
+    assert np.array_equal(l_w, w[l_idx]) and np.array_equal(h_w, w[h_idx])
+    assert len(l_idx) + len(h_idx) == 1000
+    assert np.any(w == avg)
+
+
+# --------------------------------------------------------------------------
+# PSA(s) == sweep bitwise on exact inputs; invariant on general inputs
+# --------------------------------------------------------------------------
+def test_sections_do_not_change_the_table_on_exact_inputs(oracle):
+    n = 1 << 16
+    w = inputs.exact_integers(n, 21, zero_frac=0.05)
+    p1, a1 = oracle.psa_build(w)
+    for chunk in (1, 3, 64, 1000, 1024, 4096):
+        p, a = oracle.psa_build(w, chunk=chunk)
+        assert np.array_equal(p, p1) and np.array_equal(a, a1), chunk
+    r = oracle.check(w, p1, a1)
+    assert r["max_rel"] <= 1e-13 and r["sum_dev"] <= 1e-15
+
+
+@pytest.mark.parametrize("gen", ["uniform", "powerlaw", "lognormal", "lognormal_sorted"])
+def test_invariant_general_inputs(oracle, gen):
+    n = 1 << 18
+    if gen == "uniform":
+        w = inputs.uniform01(n, 3)
+    elif gen == "powerlaw":
+        w = inputs.power_law(n, 1.0, 3)
+    elif gen == "lognormal":
+        w = inputs.lognormal(n, 2.0, 3)
+    else:
+        w = inputs.sorted_descending(inputs.lognormal(n, 2.0, 3))
+    for chunk in (1024, n):
+        prob, alias = oracle.psa_build(w, chunk=chunk)
+        r = oracle.check(w, prob, alias)
+        assert r["max_rel"] <= 1e-12, (gen, chunk, r)
+        assert r["sum_dev"] <= 1e-12
+    pv, av = oracle.vose_build(w)
+    r = oracle.check(w, pv, av)
+    assert r["max_rel"] <= 1e-12, ("vose", gen, r)
+
+
+def test_vose_is_a_valid_table_on_exact_inputs(oracle):
+    w = inputs.exact_integers(5000, 8, zero_frac=0.1)
+    p, a = oracle.vose_build(w)
+    r = oracle.check(w, p, a)
+    assert r["max_rel"] <= 1e-13 and r["zero_violations"] == 0
+
+
+# --------------------------------------------------------------------------
+# The checker catches planted mistakes (planted in the oracle's output, CPU)
+# --------------------------------------------------------------------------
+def test_checker_catches_planted_errors(oracle):
+    w = inputs.uniform01(4096, 1)
+    prob, alias = oracle.psa_build(w, chunk=256)
+    assert oracle.check(w, prob, alias)["max_rel"] <= 1e-12
+    p2 = prob.copy()
+    k = int(np.argmax(p2 < 0.9))
+    p2[k] += 1e-9
+    assert oracle.check(w, p2, alias)["max_rel"] > 1e-12
+    a2 = alias.copy()
+    k = int(np.argmax(prob < 0.5))
+    a2[k] = (a2[k] + 1) % 4096
+    assert oracle.check(w, prob, a2)["max_rel"] > 1e-12
+    a3 = alias.copy()
+    a3[0] = 4096
+    with pytest.raises(Exception):
+        oracle.check(w, prob, a3)
+
+
+def test_checker_mass_equals_exact(oracle):
+    rng = np.random.default_rng(0)
+    n = 40
+    prob = rng.random(n)
+    alias = rng.integers(0, n, n).astype(np.uint32)
+    hi, lo = oracle.mass(prob, alias)
+    em = exact.mass([Fraction(float(p)) for p in prob], alias.tolist())
+    for i in range(n):
+        assert Fraction(hi[i]) + Fraction(lo[i]) == em[i]
+
+
+# --------------------------------------------------------------------------
+# Invalid input
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bad", [[1.0, -1.0], [1.0, float("nan")], [float("inf"), 1.0],
+                                 [0.0, 0.0]])
+def test_invalid_weights(oracle, bad):
+    with pytest.raises(oracle.OracleError):
+        oracle.psa_build(np.array(bad))
+
+
+def test_empty_is_invalid(oracle):
+    with pytest.raises(oracle.OracleError):
+        oracle.total(np.zeros(0))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 against rocRAND's engine (an independent implementation)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    src = os.path.join(HERE, "rocrand_philox_ref.cpp")
+    if not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h") or not shutil.which("g++"):
+        pytest.skip("rocRAND header or g++ not available")
+    exe = str(tmp_path_factory.mktemp("philox") / "philox_ref")
+    subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", src, "-o", exe],
+                   check=True)
+
+    def run(blocks):
+        text = "\n".join(" ".join(str(int(v)) for v in b) for b in blocks) + "\n"
+        out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+        return [tuple(int(x) for x in line.split()) for line in out.strip().splitlines()]
+
+    return run
+
+
+def test_philox_matches_rocrand(oracle, rocrand_philox):
+    rng = np.random.default_rng(123)
+    blocks = [(0, 0, 0, 0, 0, 0), (2**32 - 1,) * 6]
+    blocks += [tuple(int(v) for v in rng.integers(0, 2**32, 6)) for _ in range(300)]
+    ref = rocrand_philox(blocks)
+    for b, r in zip(blocks, ref):
+        assert tuple(int(v) for v in oracle.philox(b[:4], b[4:])) == r
+
+
+def test_sampler_counter_layout_against_rocrand(oracle, rocrand_philox):
+    # A table whose rows all keep their item (prob 1) exposes the row map:
+    # draw t of table tau uses counter (t lo, t hi, tau, 0), key (seed lo, seed hi)
+    n = 1000003 % (2**20) + 17
+    prob = np.ones(n)
+    alias = np.arange(n, dtype=np.uint32)
+    seed = 0x123456789ABCDEF
+    first = 2**32 - 5
+    out = oracle.sample(prob, alias, 10, seed, first=first, table=7)
+    blocks = [((first + q) & 0xFFFFFFFF, (first + q) >> 32, 7, 0, seed & 0xFFFFFFFF, seed >> 32)
+              for q in range(10)]
+    ref = rocrand_philox(blocks)
+    rows = [((r[0] | (r[1] << 32)) * n) >> 64 for r in ref]
+    assert out.tolist() == rows
+
+
+# --------------------------------------------------------------------------
+# Sampling: exact output law of the integer Walker map, and chi-squared
+# --------------------------------------------------------------------------
+def test_sampler_exact_distribution_matches_masses(oracle):
+    w = inputs.uniform01(23, 4)
+    prob, alias = oracle.psa_build(w)
+    dist = exact.sampler_distribution(prob.tolist(), alias.tolist())
+    n = len(w)
+    fr_w = [Fraction(float(x)) for x in w]
+    W = sum(fr_w)
+    bound = Fraction(1, 2**53) + Fraction(n, 2**64) + Fraction(1, 10**14)
+    for i in range(n):
+        assert abs(dist[i] - fr_w[i] / W) <= bound
+
+
+def test_sampler_chi_squared(oracle):
+    w = inputs.power_law(5000, 1.0, 8)
+    prob, alias = oracle.psa_build(w, chunk=1024)
+    draws = 2_000_000
+    out = oracle.sample(prob, alias, draws, inputs.SAMPLE_SEED)
+    counts = np.bincount(out, minlength=len(w))
+    stat, dof, p = oracle.chi2_gof(counts, draws * w / w.sum())
+    assert p >= 1e-3, (stat, dof, p)
+
+
+def test_sampler_first_draw_offset_is_a_window(oracle):
+    w = inputs.uniform01(1000, 2)
+    prob, alias = oracle.psa_build(w)
+    a = oracle.sample(prob, alias, 5000, 99)
+    b = oracle.sample(prob, alias, 1000, 99, first=2000)
+    assert np.array_equal(a[2000:3000], b)
+    c = oracle.sample(prob, alias, 1000, 99, first=2000, table=1)
+    assert not np.array_equal(b, c)
