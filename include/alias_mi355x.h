@@ -1,0 +1,164 @@
+/*
+ * alias_mi355x.h -- C ABI of the MI355X alias-table library.
+ *
+ * Weighted random sampling with replacement (Lehmann, Huebschle-Schneider &
+ * Sanders, "Weighted Random Sampling on GPUs", arXiv 2106.12270): items
+ * 0..n-1 with weights w_i >= 0, total W, each draw returns item i with
+ * probability w_i / W (Sec. 1).  An alias table has one row per item; row k
+ * is a bucket of W/n weight split between item k (share prob[k]) and item
+ * alias[k] (share 1 - prob[k]) (Sec. 2.2, "Alias Tables").  The table is
+ * built in parallel by the PSA method (Sec. 2.2, "Parallel Construction";
+ * Sec. 4): partition into light (w <= W/n) and heavy items, prefix sums,
+ * split into sections, and an independent sweep per section that packs
+ * light items with heavy aliases.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* or described as "device" are device pointers in
+ *     the current HIP device's memory.  The caller owns every buffer; the
+ *     library allocates nothing on these paths.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on it; no entry point synchronises the device,
+ *     reads data back to the host, or allocates, so the calls can be
+ *     captured into a HIP graph.
+ *   - Indices are 0-based (the paper's are 1-based).  n is limited to
+ *     [1, 2^32 - 1] because aliases are 32-bit.
+ *   - Argument errors are reported synchronously by the return value with
+ *     nothing enqueued.  Errors that depend on the data (a weight that is
+ *     negative, NaN or infinite, or W == 0) are written by the device to
+ *     *d_status, which the caller reads after synchronising; the table's
+ *     contents are then unspecified.
+ */
+#ifndef ALIAS_MI355X_H
+#define ALIAS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (return values and *d_status). */
+enum {
+  ALIAS_OK = 0,
+  ALIAS_EINVAL = -1,     /* bad argument: NULL pointer, n out of range, bad option */
+  ALIAS_EWEIGHTS = -2,   /* device-detected: negative / NaN / infinite weight or W == 0 */
+  ALIAS_EWORKSPACE = -3, /* workspace smaller than alias_build_workspace_bytes() */
+  ALIAS_EHIP = -4,       /* a HIP launch failed (see hipGetLastError) */
+  ALIAS_EMODEL = -5,     /* learned split requested without a usable model */
+  ALIAS_EINTERNAL = -6   /* device-detected: an internal consistency check failed
+                            (section bounds); the table is not written */
+};
+
+/* Split methods (how each section's starting state is found, Sec. 4.1). */
+enum {
+  ALIAS_SPLIT_BINARY = 0, /* binary search on the light/heavy prefix sums */
+  ALIAS_SPLIT_LEARNED = 1 /* model prediction + bracket check + search in the
+                             bracket; full binary search when the bracket fails */
+};
+
+/* Build options; a zero-initialised struct selects the defaults. */
+typedef struct alias_build_opts {
+  uint32_t chunk_items;    /* rows per section (Sec. 2.2 "N/s items"): a power of
+                              two in [64, 2048]; 0 selects 1024 */
+  uint32_t split_method;   /* ALIAS_SPLIT_* */
+  const void *split_model; /* device pointer to a model blob written by
+                              alias_split_model_fit() (learned method only) */
+  uint64_t split_model_bytes; /* size of that blob; the device ignores a model
+                                 whose declared parameters do not fit in it */
+  uint32_t reserved[2];    /* must be zero */
+} alias_build_opts;
+
+/* Device-side header at the start of a build workspace (read-only for the
+ * caller; exposed so tests and tools can inspect a finished build). */
+typedef struct alias_ws_header {
+  double W_hi, W_lo;       /* total weight W, double-double */
+  double avg_hi, avg_lo;   /* bucket size W/n, double-double */
+  uint64_t L, H;           /* number of light and heavy items */
+  double sl_hi, sl_lo;     /* sum of light weights */
+  double sh_hi, sh_lo;     /* sum of heavy weights */
+  uint32_t tile_ticket;    /* internal: partition tile counter */
+  int32_t fx_exp;          /* internal: exponent of the fixed-point carry */
+  int32_t status;          /* ALIAS_OK or ALIAS_EWEIGHTS */
+  uint32_t split_fallbacks;/* learned split: sections that needed the full search */
+  uint32_t pad[4];
+} alias_ws_header;
+
+/* Byte offsets of the intermediate arrays inside a build workspace, so that
+ * the partition, prefix sums and splits of a finished build can be read back
+ * for inspection.  All offsets are relative to the workspace pointer. */
+typedef struct alias_ws_layout {
+  uint64_t header;          /* alias_ws_header */
+  uint64_t l_idx, l_w;      /* light items in index order: uint32 ids, double weights */
+  uint64_t h_idx, h_w;      /* heavy items in index order */
+  uint64_t agg_l, agg_h;    /* double-double prefix sums (hi, lo pairs) of the
+                               light / heavy weights at every agg_stride-th entry:
+                               agg_l[q] = sum of the first q*agg_stride light weights */
+  uint64_t split_i, split_j;/* uint32: lights used / heavies closed after m_k rows */
+  uint64_t spill;           /* double-double residual of the current heavy item */
+  uint64_t total_bytes;     /* == alias_build_workspace_bytes() */
+  uint32_t sections;        /* s = ceil(n / chunk_items); s+1 split entries */
+  uint32_t agg_stride;      /* 64 */
+  uint32_t tiles;           /* partition tiles */
+  uint32_t reduce_blocks;
+} alias_ws_layout;
+
+/* Workspace size in bytes for alias_build on n items (host function, no
+ * device work).  Returns 0 if n or opts are invalid.  The workspace holds the
+ * partition (12 bytes per item per list), prefix sums and splits; about
+ * 24*n + small bytes. */
+size_t alias_build_workspace_bytes(uint64_t n, const alias_build_opts *opts);
+
+/* Fill *out with the workspace layout for (n, opts).  Returns ALIAS_OK or
+ * ALIAS_EINVAL. */
+int alias_workspace_layout(uint64_t n, const alias_build_opts *opts, alias_ws_layout *out);
+
+/* Build the alias table of w[0..n) (Sec. 2.2 "Parallel Construction"; Sec. 4).
+ *   d_w       device, n doubles, read only.  Weights must be finite and >= 0
+ *             with a positive total (checked on the device -> *d_status).
+ *   d_prob    device, n doubles: prob[k] in [0, 1] is item k's share of
+ *             row k, in buckets of W/n (the paper stores the unnormalised
+ *             weight T^w_k = prob[k] * W/n).
+ *   d_alias   device, n uint32: the item that owns the rest of row k.
+ *   d_ws      device workspace of ws_bytes >= alias_build_workspace_bytes(),
+ *             256-byte aligned; contents on entry are ignored; after the
+ *             call it holds the intermediate arrays described by
+ *             alias_ws_layout.
+ *   d_status  device int32, written with ALIAS_OK, ALIAS_EWEIGHTS or
+ *             ALIAS_EINTERNAL.
+ *   opts      host pointer or NULL for defaults.
+ * The result is deterministic: the same weights and options give the same
+ * table bit for bit on every run.  Every item i ends with total share
+ * n*w_i/W of the n rows up to rounding (relative error about 1e-15 per item
+ * for typical inputs).  Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE,
+ * ALIAS_EMODEL or ALIAS_EHIP. */
+int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
+                size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts, void *stream);
+
+/* Draw `count` samples with replacement from a table (Sec. 2.2 Walker draw;
+ * Sec. 5 baseline sampling: one draw per thread).
+ * Draw t (t = first_draw .. first_draw+count-1) takes one Philox4x32-10 block
+ * with counter (t mod 2^32, t div 2^32, table_id, 0) and key (seed mod 2^32,
+ * seed div 2^32), output words r0..r3.  Row k = floor(x * n / 2^64) with
+ * x = r0 + 2^32 r1; coin u = (r2 + 2^32 r3) >> 11; the draw is k if
+ * u * 2^-53 < prob[k], else alias[k].  Every step is integer or exact, so
+ * results are reproducible bit for bit and independent of the launch shape;
+ * any window of draws can be regenerated from first_draw.
+ *   d_prob, d_alias  device table of n rows (as written by alias_build)
+ *   d_out            device, count uint32, out[q] = draw first_draw + q
+ * Returns ALIAS_OK, ALIAS_EINVAL or ALIAS_EHIP. */
+int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint64_t count,
+                 uint64_t seed, uint64_t first_draw, uint32_t table_id, uint32_t *d_out,
+                 void *stream);
+
+/* Human-readable text of a status code (static string). */
+const char *alias_status_str(int code);
+
+/* Library version string (static). */
+const char *alias_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALIAS_MI355X_H */

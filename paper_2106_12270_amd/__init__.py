@@ -1,0 +1,248 @@
+"""MI355X alias tables: PSA construction and Walker sampling (arXiv 2106.12270).
+
+Thin ctypes binding over ``libalias_mi355x.so`` (C ABI in
+``include/alias_mi355x.h``).  Argument marshalling only: every step of the
+build and of sampling runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: importing
+works anywhere, but every call needs the built library and a GPU.
+"""
+import ctypes as C
+import os
+
+__all__ = [
+    "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
+    "sample", "Builder", "status_str", "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
+    "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libalias_mi355x.so")
+
+ALIAS_OK, ALIAS_EINVAL, ALIAS_EWEIGHTS, ALIAS_EWORKSPACE, ALIAS_EHIP, ALIAS_EMODEL = (
+    0, -1, -2, -3, -4, -5)
+ALIAS_EINTERNAL = -6
+SPLIT_BINARY, SPLIT_LEARNED = 0, 1
+
+
+class AliasError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {status_str(code)} ({code})" if what else status_str(code))
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [
+        ("chunk_items", C.c_uint32),
+        ("split_method", C.c_uint32),
+        ("split_model", C.c_void_p),
+        ("split_model_bytes", C.c_uint64),
+        ("reserved", C.c_uint32 * 2),
+    ]
+
+
+class WsLayout(C.Structure):
+    _fields_ = [(name, C.c_uint64) for name in (
+        "header", "l_idx", "l_w", "h_idx", "h_w", "agg_l", "agg_h", "split_i", "split_j", "spill",
+        "total_bytes")] + [(name, C.c_uint32) for name in (
+            "sections", "agg_stride", "tiles", "reduce_blocks")]
+
+
+class WsHeader(C.Structure):
+    _fields_ = [
+        ("W_hi", C.c_double), ("W_lo", C.c_double), ("avg_hi", C.c_double),
+        ("avg_lo", C.c_double), ("L", C.c_uint64), ("H", C.c_uint64), ("sl_hi", C.c_double),
+        ("sl_lo", C.c_double), ("sh_hi", C.c_double), ("sh_lo", C.c_double),
+        ("tile_ticket", C.c_uint32), ("fx_exp", C.c_int32), ("status", C.c_int32),
+        ("split_fallbacks", C.c_uint32), ("pad", C.c_uint32 * 4),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                "g.build()'` (there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32
+        L.alias_build_workspace_bytes.argtypes = [u64, C.POINTER(BuildOpts)]
+        L.alias_build_workspace_bytes.restype = C.c_size_t
+        L.alias_workspace_layout.argtypes = [u64, C.POINTER(BuildOpts), C.POINTER(WsLayout)]
+        L.alias_workspace_layout.restype = C.c_int
+        L.alias_build.argtypes = [vp, u64, vp, vp, vp, C.c_size_t, vp, C.POINTER(BuildOpts), vp]
+        L.alias_build.restype = C.c_int
+        L.alias_sample.argtypes = [vp, vp, u64, u64, u64, u64, u32, vp, vp]
+        L.alias_sample.restype = C.c_int
+        L.alias_status_str.argtypes = [C.c_int]
+        L.alias_status_str.restype = C.c_char_p
+        L.alias_version.argtypes = []
+        L.alias_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_str(code):
+    try:
+        return lib().alias_status_str(int(code)).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def _opts(chunk=None, split="binary", model=None):
+    o = BuildOpts()
+    o.chunk_items = 0 if chunk is None else int(chunk)
+    if split in ("binary", SPLIT_BINARY):
+        o.split_method = SPLIT_BINARY
+    elif split in ("learned", SPLIT_LEARNED):
+        o.split_method = SPLIT_LEARNED
+        if model is not None:
+            o.split_model = model.data_ptr()
+            o.split_model_bytes = model.numel() * model.element_size()
+    else:
+        raise ValueError(f"unknown split method {split!r}")
+    return o
+
+
+def workspace_bytes(n, chunk=None, split="binary"):
+    o = _opts(chunk, split)
+    b = lib().alias_build_workspace_bytes(int(n), C.byref(o))
+    if b == 0:
+        raise AliasError(ALIAS_EINVAL, "workspace_bytes")
+    return b
+
+
+def layout(n, chunk=None, split="binary"):
+    o = _opts(chunk, split)
+    out = WsLayout()
+    st = lib().alias_workspace_layout(int(n), C.byref(o), C.byref(out))
+    if st:
+        raise AliasError(st, "layout")
+    return out
+
+
+def _stream(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, dtype, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+
+
+class Builder:
+    """Owns a workspace and status word for repeated builds of n items."""
+
+    def __init__(self, n, chunk=None, split="binary", model=None, device="cuda"):
+        import torch
+
+        self.n = int(n)
+        self.chunk = chunk
+        self.split = split
+        self.model = model
+        self.opts = _opts(chunk, split, model)
+        self.ws_bytes = workspace_bytes(self.n, chunk, split)
+        self.layout = layout(self.n, chunk, split)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def set_model(self, model):
+        self.model = model
+        self.opts = _opts(self.chunk, "learned" if model is not None else self.split, model)
+
+    def build(self, w, prob=None, alias=None, stream=None):
+        import torch
+
+        _check_dev(w, torch.float64, "w")
+        if w.numel() != self.n:
+            raise ValueError("w has the wrong length for this builder")
+        if prob is None:
+            prob = torch.empty(self.n, dtype=torch.float64, device=w.device)
+        if alias is None:
+            alias = torch.empty(self.n, dtype=torch.int32, device=w.device)
+        _check_dev(prob, torch.float64, "prob")
+        _check_dev(alias, torch.int32, "alias")
+        st = lib().alias_build(C.c_void_p(w.data_ptr()), self.n, C.c_void_p(prob.data_ptr()),
+                               C.c_void_p(alias.data_ptr()), C.c_void_p(self.ws.data_ptr()),
+                               self.ws_bytes, C.c_void_p(self.status.data_ptr()),
+                               C.byref(self.opts), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_build")
+        return prob, alias
+
+    # --- inspection of the last build (reads device memory; synchronises) ---
+    def _view(self, off, count, dtype):
+        import torch
+
+        es = torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + count * es].view(dtype)
+
+    def header(self):
+        import torch
+
+        raw = self.ws[self.layout.header:self.layout.header + C.sizeof(WsHeader)].cpu().numpy()
+        return WsHeader.from_buffer_copy(raw.tobytes())
+
+    def intermediates(self):
+        """Partition, prefix sums and splits of the last build as numpy arrays."""
+        import torch
+
+        h = self.header()
+        L, H = int(h.L), int(h.H)
+        lay = self.layout
+        s = int(lay.sections)
+        stride = int(lay.agg_stride)
+        out = dict(header=h, L=L, H=H)
+        out["l_idx"] = self._view(lay.l_idx, L, torch.int32).cpu().numpy().view("uint32")
+        out["l_w"] = self._view(lay.l_w, L, torch.float64).cpu().numpy()
+        out["h_idx"] = self._view(lay.h_idx, H, torch.int32).cpu().numpy().view("uint32")
+        out["h_w"] = self._view(lay.h_w, H, torch.float64).cpu().numpy()
+        out["agg_l"] = self._view(lay.agg_l, 2 * (L // stride + 1), torch.float64).cpu().numpy().reshape(-1, 2)
+        out["agg_h"] = self._view(lay.agg_h, 2 * (H // stride + 1), torch.float64).cpu().numpy().reshape(-1, 2)
+        out["split_i"] = self._view(lay.split_i, s + 1, torch.int32).cpu().numpy().view("uint32")
+        out["split_j"] = self._view(lay.split_j, s + 1, torch.int32).cpu().numpy().view("uint32")
+        out["spill"] = self._view(lay.spill, 2 * (s + 1), torch.float64).cpu().numpy().reshape(-1, 2)
+        return out
+
+
+def build(w, chunk=None, split="binary", model=None, stream=None, check=True):
+    """Build the alias table of a float64 CUDA tensor.  Returns (prob, alias)
+    with alias as int32 (bit pattern of the uint32 ids).  With check=True the
+    device status is read back (synchronises) and errors raise."""
+    b = Builder(w.numel(), chunk, split, model, device=w.device)
+    prob, alias = b.build(w, stream=stream)
+    if check:
+        st = int(b.status.item())
+        if st:
+            raise AliasError(st, "alias_build")
+    return prob, alias
+
+
+def sample(prob, alias, count, seed, first_draw=0, table_id=0, out=None, stream=None):
+    """Draw `count` samples (int32 tensor holding uint32 item ids)."""
+    import torch
+
+    _check_dev(prob, torch.float64, "prob")
+    _check_dev(alias, torch.int32, "alias")
+    if out is None:
+        out = torch.empty(int(count), dtype=torch.int32, device=prob.device)
+    _check_dev(out, torch.int32, "out")
+    if out.numel() < count:
+        raise ValueError("out is too small")
+    st = lib().alias_sample(C.c_void_p(prob.data_ptr()), C.c_void_p(alias.data_ptr()),
+                            prob.numel(), int(count), int(seed) & (2**64 - 1), int(first_draw),
+                            int(table_id), C.c_void_p(out.data_ptr()), _stream(stream))
+    if st:
+        raise AliasError(st, "alias_sample")
+    return out

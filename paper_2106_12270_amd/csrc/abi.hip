@@ -1,0 +1,87 @@
+// C entry points of the alias-table library (declared in alias_mi355x.h).
+// Argument checking and launch plumbing only: all work happens in the
+// kernels of build.hip and sample.hip.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "alias_mi355x.h"
+#include "common.hpp"
+#include "learned.hpp"
+
+namespace amdalias {
+int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
+                 int32_t *d_status, const Layout &Lo, const SplitModel *model, uint64_t model_bytes,
+                 hipStream_t st);
+int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
+                  uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st);
+}  // namespace amdalias
+
+using namespace amdalias;
+
+static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+extern "C" {
+
+size_t alias_build_workspace_bytes(uint64_t n, const alias_build_opts *opts) {
+  Layout L;
+  if (!compute_layout(n, opts, &L)) return 0;
+  return (size_t)L.pub.total_bytes;
+}
+
+int alias_workspace_layout(uint64_t n, const alias_build_opts *opts, alias_ws_layout *out) {
+  if (!out) return ALIAS_EINVAL;
+  Layout L;
+  if (!compute_layout(n, opts, &L)) return ALIAS_EINVAL;
+  *out = L.pub;
+  return ALIAS_OK;
+}
+
+int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
+                size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts, void *stream) {
+  Layout L;
+  if (!d_w || !d_prob || !d_alias || !d_ws || !d_status) return ALIAS_EINVAL;
+  if (!aligned(d_w, 8) || !aligned(d_prob, 8) || !aligned(d_alias, 4) || !aligned(d_ws, 256) ||
+      !aligned(d_status, 4))
+    return ALIAS_EINVAL;
+  if (!compute_layout(n, opts, &L)) return ALIAS_EINVAL;
+  if (ws_bytes < L.pub.total_bytes) return ALIAS_EWORKSPACE;
+  const SplitModel *model = nullptr;
+  uint64_t model_bytes = 0;
+  if (opts && opts->split_method == ALIAS_SPLIT_LEARNED) {
+    if (!opts->split_model || opts->split_model_bytes < 16 || !aligned(opts->split_model, 4))
+      return ALIAS_EMODEL;
+    model = (const SplitModel *)opts->split_model;
+    model_bytes = opts->split_model_bytes;
+  }
+  return launch_build(d_w, n, d_prob, d_alias, d_ws, d_status, L, model, model_bytes,
+                      (hipStream_t)stream);
+}
+
+int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint64_t count,
+                 uint64_t seed, uint64_t first_draw, uint32_t table_id, uint32_t *d_out,
+                 void *stream) {
+  if (n == 0 || n > 0xFFFFFFFFull) return ALIAS_EINVAL;
+  if (count == 0) return ALIAS_OK;
+  if (!d_prob || !d_alias || !d_out) return ALIAS_EINVAL;
+  if (!aligned(d_prob, 8) || !aligned(d_alias, 4) || !aligned(d_out, 4)) return ALIAS_EINVAL;
+  if (first_draw + count < first_draw) return ALIAS_EINVAL;  // counter range wraps
+  return launch_sample(d_prob, d_alias, n, count, seed, first_draw, table_id, d_out,
+                       (hipStream_t)stream);
+}
+
+const char *alias_status_str(int code) {
+  switch (code) {
+    case ALIAS_OK: return "ok";
+    case ALIAS_EINVAL: return "invalid argument";
+    case ALIAS_EWEIGHTS: return "invalid weights (negative, NaN, infinite, or zero total)";
+    case ALIAS_EWORKSPACE: return "workspace too small";
+    case ALIAS_EHIP: return "HIP launch failed";
+    case ALIAS_EMODEL: return "learned split requested without a usable model";
+    case ALIAS_EINTERNAL: return "internal consistency check failed";
+    default: return "unknown status";
+  }
+}
+
+const char *alias_version(void) { return "alias_mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

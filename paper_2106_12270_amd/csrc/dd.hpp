@@ -1,0 +1,133 @@
+// Double-double arithmetic for the device.
+//
+// A value is the unevaluated sum hi + lo of two binary64 numbers with
+// |lo| <= ulp(hi)/2, about 106 significant bits.  The alias-table build keeps
+// the total weight W, the bucket size W/N, every prefix sum, split residual
+// ("spill") and running residual in this format: the paper fixes only the
+// 64-bit type for weights and table rows, and plain binary64 sums lose the
+// per-item mass bound at the table sizes served here.
+//
+// Building blocks: Knuth's TwoSum, Dekker's FastTwoSum and the exact product
+// via fused multiply-add; the accurate addition of Hida, Li & Bailey's QD
+// library.  The whole library is compiled with -ffp-contract=off, so every
+// + and * below is one correctly rounded IEEE operation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amdalias {
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd dd_make(double hi, double lo) {
+  dd r;
+  r.hi = hi;
+  r.lo = lo;
+  return r;
+}
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double v = s - a;
+  return dd_make(s, (a - (s - v)) + (b - v));
+}
+
+// |a| >= |b| (or a == 0)
+__device__ __forceinline__ dd quick_two_sum(double a, double b) {
+  double s = a + b;
+  return dd_make(s, b - (s - a));
+}
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return dd_make(p, __fma_rn(a, b, -p));
+}
+
+__device__ __forceinline__ dd operator+(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ dd operator-(dd a) { return dd_make(-a.hi, -a.lo); }
+__device__ __forceinline__ dd operator-(dd a, dd b) { return a + (-b); }
+
+__device__ __forceinline__ dd add_d(dd a, double b) {
+  dd s = two_sum(a.hi, b);
+  s.lo += a.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ __forceinline__ dd mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ __forceinline__ dd div_d(dd a, double b) {
+  double q1 = a.hi / b;
+  dd p = two_prod(q1, b);
+  dd s = two_sum(a.hi, -p.hi);
+  s.lo -= p.lo;
+  s.lo += a.lo;
+  double q2 = (s.hi + s.lo) / b;
+  return quick_two_sum(q1, q2);
+}
+
+__device__ __forceinline__ bool le(dd a, dd b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo <= b.lo);
+}
+
+// a / b rounded to one binary64: long-division step q1, remainder-based
+// correction q2, one rounding of q1 + q2 (the correctly rounded quotient
+// whenever a and b are plain doubles).
+__device__ __forceinline__ double quot(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = a - mul_d(b, q1);
+  double q2 = r.hi / b.hi;
+  return q1 + q2;
+}
+
+__device__ __forceinline__ double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
+
+// ---------------------------------------------------------------------------
+// Wave64 shuffles of dd values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ dd shfl_up(dd v, int d) {
+  return dd_make(__shfl_up(v.hi, d, 64), __shfl_up(v.lo, d, 64));
+}
+__device__ __forceinline__ dd shfl_xor(dd v, int m) {
+  return dd_make(__shfl_xor(v.hi, m, 64), __shfl_xor(v.lo, m, 64));
+}
+__device__ __forceinline__ dd shfl(dd v, int src) {
+  return dd_make(__shfl(v.hi, src, 64), __shfl(v.lo, src, 64));
+}
+
+// Inclusive scan across the 64 lanes (Hillis-Steele, fixed pattern: the
+// result depends only on the inputs, never on timing).
+__device__ __forceinline__ dd wave_inclusive_scan(dd v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    dd o = shfl_up(v, d);
+    if (lane >= d) v = o + v;
+  }
+  return v;
+}
+
+// Sum over the 64 lanes (butterfly; every lane gets the same value).
+__device__ __forceinline__ dd wave_sum(dd v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    dd o = shfl_xor(v, m);
+    // combine in lane order so both partners compute the identical sum
+    v = ((__lane_id() & m) == 0) ? (v + o) : (o + v);
+  }
+  return v;
+}
+
+}  // namespace amdalias

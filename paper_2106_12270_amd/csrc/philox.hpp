@@ -1,0 +1,37 @@
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11), device side.
+//
+// One block maps a 128-bit counter and a 64-bit key to 128 random bits by ten
+// rounds; each round multiplies two counter words by fixed odd constants
+// (32x32 -> 64 bits), swaps the halves into place and mixes in the key, and
+// the key advances by a Weyl increment between rounds.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amdalias {
+
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t lo0 = M0 * c.x, hi0 = __umulhi(M0, c.x);
+    uint32_t lo1 = M1 * c.z, hi1 = __umulhi(M1, c.z);
+    u32x4 n;
+    n.x = hi1 ^ c.y ^ k0;
+    n.y = lo1;
+    n.z = hi0 ^ c.w ^ k1;
+    n.w = lo0;
+    c = n;
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+}  // namespace amdalias

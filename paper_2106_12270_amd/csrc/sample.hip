@@ -1,0 +1,77 @@
+// Walker sampling with replacement (arXiv 2106.12270, Sec. 2.2 "Alias
+// Tables"; Sec. 5 baseline method: each thread draws independently).
+//
+// Draw t: one Philox4x32-10 block, counter (t lo, t hi, table, 0), key
+// (seed lo, seed hi).  Row k = floor(x * n / 2^64) (64x64 multiply-high) with
+// x the first two output words; coin u = the last two words >> 11 (53 bits);
+// the draw is k if u * 2^-53 < prob[k], else alias[k].  Integer and exact
+// operations only, so every launch shape gives the same bits.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace amdalias {
+
+constexpr int kSampleThreads = 256;
+constexpr int kSampleUnroll = 4;
+
+__device__ __forceinline__ void draw_setup(uint64_t t, uint32_t table, uint32_t k0, uint32_t k1,
+                                           uint64_t n, uint64_t &row, double &coin) {
+  u32x4 c;
+  c.x = (uint32_t)t;
+  c.y = (uint32_t)(t >> 32);
+  c.z = table;
+  c.w = 0u;
+  const u32x4 r = philox4x32_10(c, k0, k1);
+  const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
+  row = __umul64hi(x, n);
+  const uint64_t u = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
+  coin = (double)u * 0x1p-53;
+}
+
+// Each thread handles kSampleUnroll consecutive grid strides per iteration so
+// that several independent row gathers are in flight per lane.
+__global__ __launch_bounds__(kSampleThreads) void k_sample(const double *__restrict__ prob,
+                                                           const uint32_t *__restrict__ alias,
+                                                           uint64_t n, uint64_t count, uint32_t k0,
+                                                           uint32_t k1, uint64_t first,
+                                                           uint32_t table,
+                                                           uint32_t *__restrict__ out) {
+  const uint64_t G = (uint64_t)gridDim.x * kSampleThreads;
+  uint64_t q = (uint64_t)blockIdx.x * kSampleThreads + threadIdx.x;
+  for (; q + (kSampleUnroll - 1) * G < count; q += kSampleUnroll * G) {
+    uint64_t row[kSampleUnroll];
+    double coin[kSampleUnroll], p[kSampleUnroll];
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u) draw_setup(first + q + u * G, table, k0, k1, n, row[u], coin[u]);
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u) p[u] = prob[row[u]];
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u) {
+      const uint32_t o = (coin[u] < p[u]) ? (uint32_t)row[u] : alias[row[u]];
+      out[q + u * G] = o;
+    }
+  }
+  for (; q < count; q += G) {
+    uint64_t row;
+    double coin;
+    draw_setup(first + q, table, k0, k1, n, row, coin);
+    const double p = prob[row];
+    out[q] = (coin < p) ? (uint32_t)row : alias[row];
+  }
+}
+
+int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
+                  uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st) {
+  if (count == 0) return ALIAS_OK;
+  uint64_t blocks = (count + kSampleThreads * 8 - 1) / (kSampleThreads * 8);
+  if (blocks > 16384) blocks = 16384;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(kSampleThreads), 0, st, prob, alias, n,
+                     count, (uint32_t)seed, (uint32_t)(seed >> 32), first, table, out);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+}  // namespace amdalias

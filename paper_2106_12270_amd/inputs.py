@@ -23,10 +23,14 @@ def uniform01(n: int, seed: int) -> np.ndarray:
 
 
 def power_law(n: int, alpha: float, seed: int) -> np.ndarray:
-    """Shuffled power law: w_i = (i+1)^-alpha for i = 0..n-1, randomly permuted."""
+    """Shuffled power law: the weights (r+1)^-alpha, r = 0..n-1, in random
+    order.  Drawn as w_i = (pi(i)+1)^-alpha for a uniformly random permutation
+    pi, which is the same distribution without a gather pass."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    w = np.arange(1, n + 1, dtype=np.float64) ** (-float(alpha))
-    return w[rng.permutation(n)]
+    w = rng.permutation(n).astype(np.float64)
+    w += 1.0
+    np.power(w, -float(alpha), out=w)
+    return w
 
 
 def lognormal(n: int, sigma: float, seed: int, mu: float = 0.0) -> np.ndarray:
@@ -116,8 +120,8 @@ def batch_zipf(sizes, seed: int, exponents=(0.5, 1.0, 1.5)):
     s_t = ex[rng.integers(0, len(ex), size=len(sizes))]
     parts = []
     for n, s in zip(sizes, s_t):
-        w = np.arange(1, int(n) + 1, dtype=np.float64) ** (-s)
-        parts.append(w[rng.permutation(int(n))])
+        w = rng.permutation(int(n)).astype(np.float64) + 1.0
+        parts.append(w ** (-s))
     return np.concatenate(parts), s_t
 
 

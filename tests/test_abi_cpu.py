@@ -1,0 +1,125 @@
+"""Host-side checks of the C-ABI library (no GPU: nothing here launches a kernel).
+
+The library loads, exports every symbol include/alias_mi355x.h declares, and
+its host logic (layout, workspace size, argument validation, status strings)
+behaves as documented.  Calls that would enqueue work are only made with
+arguments the library must reject before touching the device.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2106_12270_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "alias_mi355x.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(alias_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    syms = declared_symbols()
+    assert "alias_build" in syms and "alias_sample" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert pkg.status_str(code) != "unknown status"
+    assert pkg.status_str(12345) == "unknown status"
+    assert b"gfx950" in pkg.lib().alias_version()
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 4096, 4097, 1 << 20, (1 << 27) + 5])
+def test_layout_is_consistent(n):
+    lay = pkg.layout(n)
+    assert lay.total_bytes == pkg.workspace_bytes(n)
+    assert lay.sections == (n + 1023) // 1024
+    assert lay.tiles == (n + 4095) // 4096
+    assert lay.agg_stride == 64
+    offs = [lay.header, lay.l_idx, lay.h_idx, lay.l_w, lay.h_w, lay.agg_l, lay.agg_h,
+            lay.split_i, lay.split_j, lay.spill]
+    assert all(o % 256 == 0 for o in offs)
+    assert offs == sorted(offs) and len(set(offs)) == len(offs)
+    assert lay.l_w + 8 * n <= lay.h_w and lay.spill + 16 * (lay.sections + 1) <= lay.total_bytes
+
+
+def test_workspace_fits_in_hbm_at_the_largest_table():
+    n = 1 << 28
+    assert pkg.workspace_bytes(n) < 26 * n + (1 << 24)
+
+
+@pytest.mark.parametrize("n,chunk", [(0, None), (1 << 32, None), (100, 48), (100, 4096), (100, 8192),
+                                     (100, 1000)])
+def test_invalid_sizes(n, chunk):
+    with pytest.raises(pkg.AliasError):
+        pkg.workspace_bytes(n, chunk)
+
+
+def test_build_rejects_bad_arguments_before_launching():
+    L = pkg.lib()
+    n = 1000
+    wsb = pkg.workspace_bytes(n)
+    o = pkg.BuildOpts()
+    fake = C.c_void_p(0x10000)  # aligned, never dereferenced: validation fails first
+    # NULL pointers
+    assert L.alias_build(None, n, fake, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert L.alias_build(fake, n, None, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert L.alias_build(fake, n, fake, fake, fake, wsb, None, C.byref(o), None) == pkg.ALIAS_EINVAL
+    # n out of range
+    assert L.alias_build(fake, 0, fake, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert L.alias_build(fake, 1 << 32, fake, fake, fake, wsb, fake, C.byref(o),
+                         None) == pkg.ALIAS_EINVAL
+    # misaligned workspace / weights
+    assert L.alias_build(fake, n, fake, fake, C.c_void_p(0x10008), wsb, fake, C.byref(o),
+                         None) == pkg.ALIAS_EINVAL
+    assert L.alias_build(C.c_void_p(0x10004), n, fake, fake, fake, wsb, fake, C.byref(o),
+                         None) == pkg.ALIAS_EINVAL
+    # workspace too small
+    assert L.alias_build(fake, n, fake, fake, fake, wsb - 1, fake, C.byref(o),
+                         None) == pkg.ALIAS_EWORKSPACE
+    # bad options
+    o2 = pkg.BuildOpts()
+    o2.chunk_items = 100
+    assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o2), None) == pkg.ALIAS_EINVAL
+    o3 = pkg.BuildOpts()
+    o3.split_method = 7
+    assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o3), None) == pkg.ALIAS_EINVAL
+    o4 = pkg.BuildOpts()
+    o4.reserved[1] = 1
+    assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o4), None) == pkg.ALIAS_EINVAL
+    # learned split without a model
+    o5 = pkg.BuildOpts()
+    o5.split_method = pkg.SPLIT_LEARNED
+    assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o5), None) == pkg.ALIAS_EMODEL
+
+
+def test_sample_rejects_bad_arguments_before_launching():
+    L = pkg.lib()
+    fake = C.c_void_p(0x10000)
+    assert L.alias_sample(fake, fake, 0, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample(fake, fake, 1 << 32, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample(None, fake, 10, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample(fake, fake, 10, 10, 1, 0, 0, None, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample(C.c_void_p(0x10004), fake, 10, 10, 1, 0, 0, fake,
+                          None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample(fake, fake, 10, 10, 1, 2**64 - 5, 0, fake, None) == pkg.ALIAS_EINVAL
+    # zero draws: nothing to do, nothing launched
+    assert L.alias_sample(fake, fake, 10, 0, 1, 0, 0, fake, None) == pkg.ALIAS_OK
+
+
+def test_product_package_does_not_use_the_oracle():
+    pkg_dir = os.path.join(ROOT, "paper_2106_12270_amd")
+    for dirpath, _, files in os.walk(pkg_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "alias_oracle" not in text, f
