@@ -1,0 +1,195 @@
+"""Benchmark: PSA alias-table build + Walker sampling on one MI355X.
+
+One step = one pass of the hot path over the workload: build the alias table
+of n resident weights (reduce, partition, split, pack) and draw the workload's
+samples from it.  Workload: n = 2^27 shuffled power-law weights
+w = (r+1)^-1 in random order, sections of 1024 rows with binary-search
+splits, 10^9 draws (Philox4x32-10, fixed seed).
+
+Prints one JSON line.  `value` is the build throughput in items/s over the
+timed steps (inputs resident in HBM); `samples_per_s` is the sampling
+throughput of the same steps.  Roofline objects use algorithmic bytes per
+launch divided by the kernel's average launch time from HIP events recorded
+on the launch stream during the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of the build per item: read w twice (16), write the
+# light/heavy lists with weights (12), read them in the pack (12), write the
+# table row (8 + 4)
+BUILD_BYTES_PER_ITEM = 52
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="powerlaw_2p27")
+    ap.add_argument("--draws", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=None,
+                    help="items in the CPU oracle's build sample (default: the workload's n)")
+    ap.add_argument("--cpu-draws", type=int, default=50_000_000,
+                    help="draws in the CPU oracle's sampling sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(name, cpu_n, draws_sample):
+    """The oracle (single-threaded C) on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2106_12270_amd import inputs
+
+    cfg = inputs.WORKLOADS[name]
+    cpu_n = cfg["n"] if cpu_n is None else cpu_n
+    w = inputs.make_weights(name, n=cpu_n)
+    t0 = time.perf_counter()
+    prob, alias = oracle.psa_build(w, chunk=cfg["chunk"])
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sample(prob, alias, draws_sample, inputs.SAMPLE_SEED)
+    t_sample = time.perf_counter() - t0
+    return {
+        "value": cpu_n / t_build,
+        "unit": "items/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"sequential PSA build (sections of {cfg['chunk']}, dd arithmetic) of "
+                  f"{cpu_n} items of the same recipe ({t_build:.2f} s) and "
+                  f"{draws_sample} Philox Walker draws ({t_sample:.2f} s)",
+        "samples_per_s": draws_sample / t_sample,
+        "host_cpu": _cpu_model(),
+        "host_threads_available": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2106_12270_amd as pkg
+    from paper_2106_12270_amd import inputs
+
+    cfg = inputs.WORKLOADS[args.workload]
+    n = cfg["n"]
+    draws = cfg["draws"] if args.draws is None else args.draws
+    chunk = cfg["chunk"]
+    dev = torch.device("cuda:0")
+    print(f"[bench] workload {args.workload} n={n} draws={draws}", file=sys.stderr, flush=True)
+
+    w_host = inputs.make_weights(args.workload)
+    w = torch.from_numpy(w_host).to(dev)
+    del w_host
+    builder = pkg.Builder(n, chunk=chunk, device=dev)
+    prob = torch.empty(n, dtype=torch.float64, device=dev)
+    alias = torch.empty(n, dtype=torch.int32, device=dev)
+    out = torch.empty(draws, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        if events:
+            events[0].record(stream)
+        builder.build(w, prob, alias, stream=stream)
+        if events:
+            events[1].record(stream)
+        pkg.sample(prob, alias, draws, inputs.SAMPLE_SEED, out=out, stream=stream)
+        if events:
+            events[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = int(builder.status.item())
+    if st:
+        raise SystemExit(f"build failed: {pkg.status_str(st)}")
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    build_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    sample_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    b_ms = float(np.mean(build_ms))
+    s_ms = float(np.mean(sample_ms))
+    print(f"[bench] timed {args.steps} steps: build {b_ms:.3f} ms, sample {s_ms:.3f} ms",
+          file=sys.stderr, flush=True)
+
+    # expected fraction of draws that read the alias column: mean(1 - prob)
+    p_alias = float((1.0 - prob).mean().item())
+    sample_bytes = draws * (4 + 8 + 4 * p_alias)
+    sample_gbs = sample_bytes / (s_ms * 1e-3) / 1e9
+    build_gbs = n * BUILD_BYTES_PER_ITEM / (b_ms * 1e-3) / 1e9
+    if s_ms >= b_ms:
+        roof = {"bound": "hbm", "achieved": round(sample_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(sample_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sample",
+                "bytes_per_launch": round(sample_bytes),
+                "bytes_model": "per draw: 4 B out + 8 B prob + 4 B alias x P(alias)",
+                "p_alias": round(p_alias, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(build_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(build_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "alias_build (all build kernels)",
+                "bytes_per_launch": n * BUILD_BYTES_PER_ITEM,
+                "bytes_model": "52 B per item"}
+
+    result = {
+        "metric": "alias build items/s (%HBM peak) + samples/s; learned vs binary split, 1 GPU",
+        "value": n / (b_ms * 1e-3),
+        "unit": "items/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "dist": cfg["dist"],
+                   "alpha": cfg.get("alpha"), "chunk": chunk, "split": "binary",
+                   "draws": draws, "parallelism": "none (1 GPU)"},
+        "build_ms": b_ms,
+        "build_hbm_frac": round(build_gbs / HBM_PEAK_GBS, 4),
+        "build_gbs": round(build_gbs, 1),
+        "sample_ms": s_ms,
+        "samples_per_s": draws / (s_ms * 1e-3),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_n, args.cpu_draws)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,8 +77,7 @@ typedef struct alias_ws_header {
   uint64_t L, H;           /* number of light and heavy items */
   double sl_hi, sl_lo;     /* sum of light weights */
   double sh_hi, sh_lo;     /* sum of heavy weights */
-  uint32_t tile_ticket;    /* internal: partition tile counter */
-  int32_t fx_exp;          /* internal: exponent of the fixed-point carry */
+  uint32_t reserved0[2];
   int32_t status;          /* ALIAS_OK or ALIAS_EWEIGHTS */
   uint32_t split_fallbacks;/* learned split: sections that needed the full search */
   uint32_t pad[4];

@@ -52,7 +52,7 @@ class WsHeader(C.Structure):
         ("W_hi", C.c_double), ("W_lo", C.c_double), ("avg_hi", C.c_double),
         ("avg_lo", C.c_double), ("L", C.c_uint64), ("H", C.c_uint64), ("sl_hi", C.c_double),
         ("sl_lo", C.c_double), ("sh_hi", C.c_double), ("sh_lo", C.c_double),
-        ("tile_ticket", C.c_uint32), ("fx_exp", C.c_int32), ("status", C.c_int32),
+        ("reserved0", C.c_uint32 * 2), ("status", C.c_int32),
         ("split_fallbacks", C.c_uint32), ("pad", C.c_uint32 * 4),
     ]
 

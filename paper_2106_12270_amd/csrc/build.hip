@@ -2,17 +2,16 @@
 // Sanders, arXiv 2106.12270, Sec. 2.2 and Sec. 4).
 //
 // Pipeline, one stream, no host synchronisation or readback:
-//   k_reduce    per-block double-double sums of the weights + validation;
-//               also clears the partition's look-back flags.
+//   k_reduce    per-block double-double sums of the weights + validation.
 //   k_finalize  W, W/N, status; resets the counters the later kernels use.
-//   k_partition stable light/heavy partition in item order, entries carry
-//               their weight (Sec. 4.2 "Weight in l and h Arrays"), light
-//               probabilities written in item order, and prefix sums of the
-//               light / heavy weights emitted every 64 entries.  Single pass:
-//               tiles take ids from a ticket and find their offsets by a
-//               decoupled look-back (Merrill & Garland) whose carries are
-//               exact 128-bit fixed-point integers, so the result does not
-//               depend on timing.
+//   k_tilesum   per 4096-item tile: light count, light and heavy weight sums;
+//               writes each item's own-row share w/avg (final for lights).
+//   k_tilescan  exclusive prefix over the tiles (one block, fixed order).
+//   k_partition stable light/heavy partition in item order with the tile
+//               offsets known; entries carry their weight (Sec. 4.2 "Weight
+//               in l and h Arrays"); prefix sums of the light / heavy weights
+//               emitted every 64 entries.
+//   Every sum is formed in a fixed order, so builds are bit-reproducible.
 //   k_split     state (lights used, heavies closed, spill) after m_k = k*C
 //               rows for every section boundary (Sec. 2.2; Sec. 4.1 binary
 //               search baseline), or the learned variant.
@@ -28,98 +27,11 @@
 
 namespace amdalias {
 
-typedef __int128 i128;
-typedef unsigned __int128 u128;
-
 // ---------------------------------------------------------------------------
-// Fixed-point helpers for the look-back carry
+// Block reductions and scans (fixed combination order: results never depend
+// on timing, so builds are bit-reproducible)
 // ---------------------------------------------------------------------------
-
-// trunc(x * 2^-E) as a signed 128-bit integer (|x * 2^-E| < 2^126 assumed).
-__device__ __forceinline__ i128 fx_from_double(double x, int E) {
-  if (x == 0.0) return 0;
-  int e;
-  double m = frexp(x, &e);  // x = m * 2^e, 0.5 <= |m| < 1
-  int sh = e - E;           // |x| * 2^-E = |m| * 2^sh
-  if (sh <= 0) return 0;
-  long long M = (long long)(m * 9007199254740992.0);  // m * 2^53, exact
-  bool neg = M < 0;
-  u128 A = (u128)(unsigned long long)(neg ? -M : M);
-  u128 U = (sh >= 53) ? (A << (sh - 53)) : (A >> (53 - sh));
-  i128 r = (i128)U;
-  return neg ? -r : r;
-}
-
-__device__ __forceinline__ i128 fx_from_dd(dd v, int E) {
-  return fx_from_double(v.hi, E) + fx_from_double(v.lo, E);
-}
-
-__device__ __forceinline__ double u128_to_double(u128 U) {
-  unsigned long long hi = (unsigned long long)(U >> 64);
-  unsigned long long lo = (unsigned long long)U;
-  return (double)hi * 18446744073709551616.0 + (double)lo;
-}
-
-__device__ __forceinline__ double i128_to_double(i128 V) {
-  return V < 0 ? -u128_to_double((u128)(-V)) : u128_to_double((u128)V);
-}
-
-__device__ __forceinline__ dd fx_to_dd(i128 V, int E) {
-  double a = i128_to_double(V);
-  i128 R = V - fx_from_double(a, 0);
-  double b = i128_to_double(R);
-  dd r = quick_two_sum(a, b);
-  r.hi = ldexp(r.hi, E);
-  r.lo = ldexp(r.lo, E);
-  return r;
-}
-
-__device__ __forceinline__ i128 u128_pack(uint64_t lo, uint64_t hi) {
-  return (i128)(((u128)hi << 64) | (u128)lo);
-}
-
-__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
-  return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish a tile descriptor: the value words go out with cache-bypassing
-// atomic stores, then (after all of them have completed) the flag.  Only
-// ordering is needed, not an L2 writeback, because every word is itself
-// coherent.
-__device__ __forceinline__ void publish(TileWords *slot, uint32_t *flag, uint32_t fval, uint64_t cnt,
-                                        i128 sl, i128 sh) {
-  st_relaxed(&slot->cnt, cnt);
-  st_relaxed(&slot->sl_lo, (uint64_t)(u128)sl);
-  st_relaxed(&slot->sl_hi, (uint64_t)((u128)sl >> 64));
-  st_relaxed(&slot->sh_lo, (uint64_t)(u128)sh);
-  st_relaxed(&slot->sh_hi, (uint64_t)((u128)sh >> 64));
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_s_waitcnt(0);
-  __hip_atomic_store(flag, fval, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-  return __shfl_xor(v, m, 64);
-}
-
-__device__ __forceinline__ i128 wave_sum_i128(i128 v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    u128 u = (u128)v;
-    unsigned long long lo = shfl_xor_u64((unsigned long long)u, m);
-    unsigned long long hi = shfl_xor_u64((unsigned long long)(u >> 64), m);
-    v += u128_pack(lo, hi);
-  }
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// Block reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ dd block_sum_dd(dd v, dd *s_wave /*[4]*/) {
+__device__ __forceinline__ dd block_sum_dd(dd v, dd *s_wave /*[blockDim/64]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   v = wave_sum(v);
   if (lane == 0) s_wave[wave] = v;
@@ -130,18 +42,21 @@ __device__ __forceinline__ dd block_sum_dd(dd v, dd *s_wave /*[4]*/) {
   return t;
 }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // k_reduce: per-block dd partial sums of w and the validation flag
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const double *__restrict__ w, uint64_t n,
-                                                           ReducePart *__restrict__ parts,
-                                                           uint32_t *__restrict__ flags,
-                                                           uint32_t tiles) {
+                                                           ReducePart *__restrict__ parts) {
   __shared__ dd s_wave[kReduceThreads / 64];
   __shared__ uint32_t s_bad;
   const uint64_t G = (uint64_t)gridDim.x * kReduceThreads;
   const uint64_t g = (uint64_t)blockIdx.x * kReduceThreads + threadIdx.x;
-  for (uint64_t t = g; t < tiles; t += G) flags[t] = 0u;
   if (threadIdx.x == 0) s_bad = 0;
   dd s = dd_make(0.0, 0.0);
   uint32_t bad = 0;
@@ -197,8 +112,7 @@ __global__ __launch_bounds__(256) void k_finalize(const ReducePart *__restrict__
     hdr->L = 0;
     hdr->H = 0;
     hdr->sl_hi = hdr->sl_lo = hdr->sh_hi = hdr->sh_lo = 0.0;
-    hdr->tile_ticket = 0;
-    hdr->fx_exp = ok ? (ilogb(W.hi) - 125) : 0;
+    hdr->reserved0[0] = hdr->reserved0[1] = 0;
     hdr->status = ok ? ALIAS_OK : ALIAS_EWEIGHTS;
     hdr->split_fallbacks = 0;
     agg_l[0] = dd_make(0.0, 0.0);
@@ -208,51 +122,185 @@ __global__ __launch_bounds__(256) void k_finalize(const ReducePart *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// k_partition
+// k_tilesum: per tile of 4096 items, the number of light items and the light
+// and heavy weight sums; also writes every item's own-row share w/avg (final
+// for light items, rewritten by k_pack for heavy ones).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kTileThreads) void k_tilesum(const double *__restrict__ w, uint64_t n,
+                                                          const alias_ws_header *hdr,
+                                                          TileSum *__restrict__ sums,
+                                                          double *__restrict__ prob) {
+  __shared__ dd s_l[kTileThreads / 64], s_h[kTileThreads / 64];
+  __shared__ uint32_t s_c[kTileThreads / 64];
+  if (hdr->status != ALIAS_OK) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t base = (uint64_t)blockIdx.x * kTileItems;
+  const dd avg = dd_make(hdr->avg_hi, hdr->avg_lo);
+  dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
+  uint32_t cnt = 0;
+#pragma unroll 4
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    const uint64_t gi = base + (uint64_t)k * kTileThreads + tid;
+    if (gi < n) {
+      const double x = w[gi];
+      const bool light = le(dd_make(x, 0.0), avg);
+      prob[gi] = clamp01(quot(dd_make(x, 0.0), avg));
+      dd a = light ? acc_l : acc_h;
+      a = add_d(a, x);
+      if (light)
+        acc_l = a;
+      else
+        acc_h = a;
+      cnt += light;
+    }
+  }
+  acc_l = wave_sum(acc_l);
+  acc_h = wave_sum(acc_h);
+  cnt = wave_sum_u32(cnt);
+  if (lane == 0) {
+    s_l[wave] = acc_l;
+    s_h[wave] = acc_h;
+    s_c[wave] = cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd tl = s_l[0], th = s_h[0];
+    uint32_t c = s_c[0];
+    for (int k = 1; k < kTileThreads / 64; ++k) {
+      tl = tl + s_l[k];
+      th = th + s_h[k];
+      c += s_c[k];
+    }
+    TileSum t;
+    t.cnt = c;
+    t.pad = 0;
+    t.sl = tl;
+    t.sh = th;
+    sums[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_tilescan: exclusive prefix over the tiles (one block, fixed order), the
+// totals, and the final prefix-sum points when a list length is a multiple
+// of the aggregate stride.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_tilescan(const TileSum *__restrict__ sums,
+                                                           uint32_t tiles, uint64_t n,
+                                                           alias_ws_header *hdr,
+                                                           TilePrefix *__restrict__ pre,
+                                                           dd *__restrict__ agg_l,
+                                                           dd *__restrict__ agg_h) {
+  __shared__ dd s_l[kScanThreads / 64], s_h[kScanThreads / 64];
+  __shared__ uint64_t s_c[kScanThreads / 64];
+  if (hdr->status != ALIAS_OK) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t per = (tiles + kScanThreads - 1) / kScanThreads;
+  const uint32_t b = tid * per;
+  const uint32_t e = (b + per < tiles) ? b + per : tiles;
+  dd sl = dd_make(0.0, 0.0), sh = dd_make(0.0, 0.0);
+  uint64_t c = 0;
+  for (uint32_t t = b; t < e; ++t) {
+    sl = sl + sums[t].sl;
+    sh = sh + sums[t].sh;
+    c += sums[t].cnt;
+  }
+  // block exclusive scan of (c, sl, sh)
+  dd il = wave_inclusive_scan(sl, lane), ih = wave_inclusive_scan(sh, lane);
+  uint64_t ic = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t o = __shfl_up(ic, d, 64);
+    if (lane >= d) ic += o;
+  }
+  if (lane == 63) {
+    s_l[wave] = il;
+    s_h[wave] = ih;
+    s_c[wave] = ic;
+  }
+  __syncthreads();
+  dd ol = dd_make(0.0, 0.0), oh = dd_make(0.0, 0.0);
+  uint64_t oc = 0;
+  dd tl = dd_make(0.0, 0.0), th = dd_make(0.0, 0.0);
+  uint64_t tc = 0;
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < wave) {
+      ol = ol + s_l[k];
+      oh = oh + s_h[k];
+      oc += s_c[k];
+    }
+    tl = tl + s_l[k];
+    th = th + s_h[k];
+    tc += s_c[k];
+  }
+  dd xl = shfl_up(il, 1), xh = shfl_up(ih, 1);
+  uint64_t xc = __shfl_up(ic, 1, 64);
+  if (lane == 0) {
+    xl = dd_make(0.0, 0.0);
+    xh = dd_make(0.0, 0.0);
+    xc = 0;
+  }
+  dd rl = ol + xl, rh = oh + xh;
+  uint64_t rc = oc + xc;
+  for (uint32_t t = b; t < e; ++t) {
+    TilePrefix p;
+    p.l_before = rc;
+    p.pl = rl;
+    p.ph = rh;
+    pre[t] = p;
+    rl = rl + sums[t].sl;
+    rh = rh + sums[t].sh;
+    rc += sums[t].cnt;
+  }
+  if (tid == 0) {
+    const uint64_t L = tc, H = n - tc;
+    hdr->L = L;
+    hdr->H = H;
+    hdr->sl_hi = tl.hi;
+    hdr->sl_lo = tl.lo;
+    hdr->sh_hi = th.hi;
+    hdr->sh_lo = th.lo;
+    if ((L & (kAggStride - 1)) == 0) agg_l[L / kAggStride] = tl;
+    if ((H & (kAggStride - 1)) == 0) agg_h[H / kAggStride] = th;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_partition: stable partition with known tile offsets
 // ---------------------------------------------------------------------------
 struct PartShared {
   double val[kTileItems + kTileItems / 16];  // staging (padded for the transpose)
   uint32_t idx[kTileItems];
   dd wl[4], wh[4];
   uint32_t cl[4], ch[4];
-  uint32_t tile;
-  uint32_t pad;
-  uint64_t l_before;
-  dd pl, ph;
 };
 
 __device__ __forceinline__ int spos(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(kTileThreads) void k_partition(
-    const double *__restrict__ w, uint64_t n, alias_ws_header *hdr, uint32_t *flags,
-    TileWords *tile_a, TileWords *tile_p, uint32_t tiles, uint32_t *__restrict__ l_idx,
-    double *__restrict__ l_w, uint32_t *__restrict__ h_idx, double *__restrict__ h_w,
-    dd *__restrict__ agg_l, dd *__restrict__ agg_h, double *__restrict__ prob) {
+    const double *__restrict__ w, uint64_t n, const alias_ws_header *hdr,
+    const TilePrefix *__restrict__ pre, uint32_t *__restrict__ l_idx, double *__restrict__ l_w,
+    uint32_t *__restrict__ h_idx, double *__restrict__ h_w, dd *__restrict__ agg_l,
+    dd *__restrict__ agg_h) {
   __shared__ PartShared S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (hdr->status != ALIAS_OK) return;
-  if (tid == 0) S.tile = atomicAdd(&hdr->tile_ticket, 1u);
-  __syncthreads();
-  const uint32_t tile = S.tile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t tile = blockIdx.x;
   const uint64_t base = (uint64_t)tile * kTileItems;
   const dd avg = dd_make(hdr->avg_hi, hdr->avg_lo);
-  const int E = hdr->fx_exp;
 
-  // 1. striped, coalesced load; light probabilities written in item order
+  // 1. striped, coalesced load into the staging area
 #pragma unroll
   for (int k = 0; k < kItemsPerThread; ++k) {
     const int e = k * kTileThreads + tid;
     const uint64_t gi = base + e;
-    double x = 0.0;
-    if (gi < n) {
-      x = w[gi];
-      prob[gi] = clamp01(quot(dd_make(x, 0.0), avg));  // heavies are rewritten by k_pack
-    }
-    S.val[spos(e)] = x;
+    S.val[spos(e)] = (gi < n) ? w[gi] : 0.0;
   }
   __syncthreads();
 
-  // 2. blocked view: thread owns items tid*16 .. tid*16+15
+  // 2. blocked view: this thread owns items tid*16 .. tid*16+15
   double x[kItemsPerThread];
   uint32_t lmask = 0, vmask = 0;
 #pragma unroll
@@ -265,14 +313,11 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
     lmask |= (uint32_t)light << u;
   }
   const uint32_t hmask = vmask & ~lmask;
-  // running sums before each item, for the item's own list
-  dd before[kItemsPerThread];
   dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
 #pragma unroll
   for (int u = 0; u < kItemsPerThread; ++u) {
     const bool light = (lmask >> u) & 1u;
     dd a = light ? acc_l : acc_h;
-    before[u] = a;
     a = add_d(a, ((vmask >> u) & 1u) ? x[u] : 0.0);
     if (light)
       acc_l = a;
@@ -281,7 +326,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
   }
   const uint32_t nl = __popc(lmask), nh = __popc(hmask);
 
-  // 3. block exclusive scans: counts (int) and sums (dd), fixed pattern
+  // 3. block exclusive scans of the counts and sums
   uint32_t cl_inc = nl, ch_inc = nh;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -299,10 +344,9 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
     S.wl[wave] = sl_inc;
     S.wh[wave] = sh_inc;
   }
-  __syncthreads();
-  uint32_t cl_off = 0, ch_off = 0, Lt = 0, Ht = 0;
+  __syncthreads();  // also: every thread has its x[] in registers
+  uint32_t cl_off = 0, ch_off = 0, Lt = 0;
   dd sl_off = dd_make(0.0, 0.0), sh_off = dd_make(0.0, 0.0);
-  dd Slt = dd_make(0.0, 0.0), Sht = dd_make(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k < wave) {
@@ -312,102 +356,45 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
       sh_off = sh_off + S.wh[k];
     }
     Lt += S.cl[k];
-    Ht += S.ch[k];
-    Slt = Slt + S.wl[k];
-    Sht = Sht + S.wh[k];
   }
-  const uint32_t l_ex = cl_off + cl_inc - nl;  // tile-local rank of this thread's first light
-  const uint32_t h_ex = ch_off + ch_inc - nh;
-  // exclusive dd prefix within the tile: wave offset + lanes before
   dd sl_lane = shfl_up(sl_inc, 1), sh_lane = shfl_up(sh_inc, 1);
   if (lane == 0) {
     sl_lane = dd_make(0.0, 0.0);
     sh_lane = dd_make(0.0, 0.0);
   }
-  const dd sl_ex = sl_off + sl_lane;
-  const dd sh_ex = sh_off + sh_lane;
-
-  // 4. decoupled look-back (wave 0) for the tile's global offsets
-  if (wave == 0) {
-    const i128 agg_sl = fx_from_dd(Slt, E), agg_sh = fx_from_dd(Sht, E);
-    uint64_t ex_cnt = 0;
-    i128 ex_sl = 0, ex_sh = 0;
-    if (tile == 0) {
-      if (lane == 0) publish(&tile_p[0], &flags[0], 2u, Lt, agg_sl, agg_sh);
-    } else {
-      if (lane == 0) publish(&tile_a[tile], &flags[tile], 1u, Lt, agg_sl, agg_sh);
-      int64_t p_end = tile;
-      while (true) {
-        const int64_t p = p_end - 1 - lane;
-        uint32_t f = 2u;
-        uint64_t c = 0;
-        i128 a = 0, b = 0;
-        if (p >= 0) {
-          f = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          while (f == 0u) {
-            __builtin_amdgcn_s_sleep(1);
-            f = __hip_atomic_load(&flags[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          __builtin_amdgcn_s_waitcnt(0);
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-          const TileWords *src = (f == 2u) ? &tile_p[p] : &tile_a[p];
-          c = ld_relaxed(&src->cnt);
-          a = u128_pack(ld_relaxed(&src->sl_lo), ld_relaxed(&src->sl_hi));
-          b = u128_pack(ld_relaxed(&src->sh_lo), ld_relaxed(&src->sh_hi));
-        }
-        const unsigned long long done = __ballot(f == 2u);
-        const int first = done ? (__ffsll((long long)done) - 1) : 64;
-        if (lane > first) {
-          c = 0;
-          a = 0;
-          b = 0;
-        }
-        // counts fit in 64 bits; reuse the 128-bit reduction for all three
-        ex_cnt += (uint64_t)wave_sum_i128((i128)c);
-        ex_sl += wave_sum_i128(a);
-        ex_sh += wave_sum_i128(b);
-        if (done) break;
-        p_end -= 64;
-      }
-      if (lane == 0)
-        publish(&tile_p[tile], &flags[tile], 2u, ex_cnt + Lt, ex_sl + agg_sl, ex_sh + agg_sh);
-    }
-    if (lane == 0) {
-      S.l_before = ex_cnt;
-      S.pl = fx_to_dd(ex_sl, E);
-      S.ph = fx_to_dd(ex_sh, E);
-    }
-  }
-  __syncthreads();  // also: every thread has read S.val into x[]
-
-  const uint64_t l_before = S.l_before;
+  const TilePrefix tp = pre[tile];
+  const uint64_t l_before = tp.l_before;
   const uint64_t h_before = base - l_before;
-  const dd pl_thr = S.pl + sl_ex;
-  const dd ph_thr = S.ph + sh_ex;
+  const dd pl_thr = tp.pl + (sl_off + sl_lane);
+  const dd ph_thr = tp.ph + (sh_off + sh_lane);
+  uint32_t rl = cl_off + cl_inc - nl;
+  uint32_t rh = Lt + ch_off + ch_inc - nh;
 
-  // 5. stage entries at their tile-local ranks; emit prefix sums every 64
-  uint32_t rl = l_ex, rh = Lt + h_ex;
+  // 4. stage entries at their tile-local ranks; emit prefix sums every 64
+  dd run_l = dd_make(0.0, 0.0), run_h = dd_make(0.0, 0.0);
 #pragma unroll
   for (int u = 0; u < kItemsPerThread; ++u) {
-    const uint64_t gi = base + (uint64_t)tid * kItemsPerThread + u;
+    const uint32_t gi = (uint32_t)(base + (uint64_t)tid * kItemsPerThread + u);
     if ((lmask >> u) & 1u) {
       const uint64_t g = l_before + rl;
-      S.idx[rl] = (uint32_t)gi;
+      S.idx[rl] = gi;
       S.val[rl] = x[u];
-      if ((g & (kAggStride - 1)) == 0) agg_l[g / kAggStride] = pl_thr + before[u];
+      if ((g & (kAggStride - 1)) == 0) agg_l[g / kAggStride] = pl_thr + run_l;
+      run_l = add_d(run_l, x[u]);
       ++rl;
     } else if ((hmask >> u) & 1u) {
       const uint64_t g = h_before + (rh - Lt);
-      S.idx[rh] = (uint32_t)gi;
+      S.idx[rh] = gi;
       S.val[rh] = x[u];
-      if ((g & (kAggStride - 1)) == 0) agg_h[g / kAggStride] = ph_thr + before[u];
+      if ((g & (kAggStride - 1)) == 0) agg_h[g / kAggStride] = ph_thr + run_h;
+      run_h = add_d(run_h, x[u]);
       ++rh;
     }
   }
   __syncthreads();
 
-  // 6. coalesced write-out of both lists
-  const uint32_t cnt = Lt + Ht;
+  // 5. coalesced write-out of both lists
+  const uint32_t cnt = (uint32_t)((n - base < (uint64_t)kTileItems) ? n - base : kTileItems);
   for (uint32_t e = tid; e < cnt; e += kTileThreads) {
     if (e < Lt) {
       l_idx[l_before + e] = S.idx[e];
@@ -416,20 +403,6 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
       h_idx[h_before + (e - Lt)] = S.idx[e];
       h_w[h_before + (e - Lt)] = S.val[e];
     }
-  }
-
-  // 7. the last tile records the totals
-  if (tile == tiles - 1 && tid == 0) {
-    const uint64_t L = l_before + Lt, H = h_before + Ht;
-    const dd slt = S.pl + Slt, sht = S.ph + Sht;
-    hdr->L = L;
-    hdr->H = H;
-    hdr->sl_hi = slt.hi;
-    hdr->sl_lo = slt.lo;
-    hdr->sh_hi = sht.hi;
-    hdr->sh_lo = sht.lo;
-    if ((L & (kAggStride - 1)) == 0) agg_l[L / kAggStride] = slt;
-    if ((H & (kAggStride - 1)) == 0) agg_h[H / kAggStride] = sht;
   }
 }
 
@@ -551,28 +524,29 @@ __global__ __launch_bounds__(256) void k_split(const alias_ws_header *hdr, const
 }
 
 // ---------------------------------------------------------------------------
-// k_pack: one wave per section
+// k_pack: one wave per section of C rows (Sec. 4.2).  The section's light
+// and heavy entries (weights and ids) are staged in LDS with coalesced loads
+// (the paper's shared-memory pack), prefix sums are formed every G = C/64
+// entries, each lane finds its start state at local row G*lane by a search
+// on those sums and a walk of at most G entries, then sweeps its G rows
+// reading only LDS.  Light aliases are staged and written out in light order.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int ppos(int e) { return e + (e >> 4); }  // padded LDS index
 
-// P[ppos(0)] = 0 and P[ppos(e+1)] = src[0] + ... + src[e] for e < cnt.
-__device__ void wave_prefix(const double *__restrict__ src, int cnt, dd *P, int lane) {
-  for (int e = lane; e < cnt; e += 64) P[ppos(e + 1)] = dd_make(src[e], 0.0);
-  if (lane == 0) P[ppos(0)] = dd_make(0.0, 0.0);
-  wave_lds_sync();
-  const int per = (cnt + 63) >> 6;
-  const int b = lane * per;
-  const int en = (b + per < cnt) ? b + per : cnt;
-  dd acc = dd_make(0.0, 0.0);
-  for (int e = b; e < en; ++e) acc = add_d(acc, P[ppos(e + 1)].hi);
-  dd inc = wave_inclusive_scan(acc, lane);
-  dd run = shfl_up(inc, 1);
-  if (lane == 0) run = dd_make(0.0, 0.0);
-  for (int e = b; e < en; ++e) {
-    run = add_d(run, P[ppos(e + 1)].hi);
-    P[ppos(e + 1)] = run;
-  }
-  wave_lds_sync();
+struct PackLds {
+  uint32_t w_off, ix_off, ao_off, q_off, bytes;
+};
+
+__host__ __device__ inline PackLds pack_lds(uint32_t chunk) {
+  PackLds p;
+  const uint32_t nw = (uint32_t)ppos((int)chunk + 2) + 1;
+  const uint32_t na = (uint32_t)ppos((int)chunk) + 1;
+  p.w_off = 0;
+  p.q_off = (8u * nw + 15u) & ~15u;
+  p.ix_off = p.q_off + 16u * 2u * 66u;
+  p.ao_off = p.ix_off + 4u * nw;
+  p.bytes = (p.ao_off + 4u * na + 15u) & ~15u;
+  return p;
 }
 
 __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
@@ -581,12 +555,17 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     const uint32_t *__restrict__ split_i, const uint32_t *__restrict__ split_j,
     const dd *__restrict__ spill, uint32_t s, uint32_t chunk, double *__restrict__ prob,
     uint32_t *__restrict__ alias, int32_t *d_status) {
-  extern __shared__ dd smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t k = blockIdx.x * (blockDim.x >> 6) + wave;
   if (k >= s || hdr->status != ALIAS_OK) return;
-  const int stride = ppos((int)chunk + 3) + 1;
-  dd *P = smem + wave * stride;
+  const PackLds PLy = pack_lds(chunk);
+  unsigned char *base = smem_raw + (size_t)wave * PLy.bytes;
+  double *Wv = (double *)(base + PLy.w_off);
+  dd *QL = (dd *)(base + PLy.q_off);
+  dd *QH = QL + 66;
+  uint32_t *Ix = (uint32_t *)(base + PLy.ix_off);
+  uint32_t *Ao = (uint32_t *)(base + PLy.ao_off);
 
   const uint64_t H = hdr->H;
   const dd avg = dd_make(hdr->avg_hi, hdr->avg_lo);
@@ -598,7 +577,6 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     if (lane == 0) *d_status = ALIAS_EINTERNAL;
     return;
   }
-
   if (j0 >= H) {  // no heavy item left: remaining lights keep their whole row
     for (int e = lane; e < nl; e += 64) {
       const uint32_t l = l_idx[i0 + e];
@@ -607,76 +585,126 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     return;
   }
   const int nhl = (nh + 1 < (int)(H - j0)) ? nh + 1 : (int)(H - j0);
-  dd *PL = P;                    // ppos(0 .. nl)
-  dd *PH = P + ppos(nl + 1);     // ppos(0 .. nhl), relative
-  wave_prefix(l_w + i0, nl, PL, lane);
-  wave_prefix(h_w + j0, nhl, PH, lane);
+  const int G = (int)(chunk >> 6);  // rows per lane == prefix-sum stride
+
+  // 1. stage the section's lights (slots 0..nl-1) and heavies (nl..nl+nhl-1)
+  for (int e = lane; e < nl; e += 64) {
+    Wv[ppos(e)] = l_w[i0 + e];
+    Ix[ppos(e)] = l_idx[i0 + e];
+  }
+  for (int e = lane; e < nhl; e += 64) {
+    Wv[ppos(nl + e)] = h_w[j0 + e];
+    Ix[ppos(nl + e)] = h_idx[j0 + e];
+  }
+  wave_lds_sync();
+
+  // 2. prefix sums every G entries: QL[q] = sum of the first min(qG, nl) lights
+  {
+    dd al = dd_make(0.0, 0.0), ah = dd_make(0.0, 0.0);
+    const int b = lane * G;
+    for (int u = 0; u < G; ++u) {
+      if (b + u < nl) al = add_d(al, Wv[ppos(b + u)]);
+      if (b + u < nhl) ah = add_d(ah, Wv[ppos(nl + b + u)]);
+    }
+    const dd il = wave_inclusive_scan(al, lane), ih = wave_inclusive_scan(ah, lane);
+    QL[lane + 1] = il;
+    QH[lane + 1] = ih;
+    if (lane == 0) {
+      QL[0] = dd_make(0.0, 0.0);
+      QH[0] = dd_make(0.0, 0.0);
+    }
+  }
+  wave_lds_sync();
 
   const dd sp0 = spill[k];
-  const dd B = sp0 - PH[ppos(1)];  // sigma offset: f_local(i,j) = PL[i] + PH[j] + B - m*avg
+  const dd B = sp0 - dd_make(Wv[ppos(nl)], 0.0);  // f_local(i, j) + B - m*avg = global f - m*avg
   const int total = nl + nh;
-  const int rpl = (int)(chunk >> 6);
 
-  // sub-split at local row m: largest j with PL[m-j] + PH[j] + B <= m*avg
-  auto subsplit = [&](int m, int &io, int &jo) {
-    if (m <= 0) {
-      io = 0;
-      jo = 0;
-      return;
-    }
-    if (m >= total) {
-      io = nl;
-      jo = nh;
-      return;
-    }
-    const dd target = mul_d(avg, (double)m) - B;
-    int lo = (m > nl) ? m - nl : 0;
-    int hi = (m < nh) ? m : nh;
-    while (lo < hi) {
-      const int mid = lo + (hi - lo + 1) / 2;
-      if (le(PL[ppos(m - mid)] + PH[ppos(mid)], target))
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    io = m - lo;
-    jo = lo;
-  };
-  int i, j, ie, je;
-  subsplit(lane * rpl, i, j);
-  subsplit((lane + 1) * rpl, ie, je);
-  if (lane * rpl >= total) return;
-
+  // 3. this lane's start state at local row m = G*lane
+  int i, j;
   dd r = dd_make(0.0, 0.0);
-  if (j0 + (uint64_t)j < H) {
-    const int m = i + j;
-    r = (B + PL[ppos(i)] + PH[ppos(j + 1)]) - mul_d(avg, (double)m);
+  {
+    const int m = G * lane;
+    if (m >= total) {
+      i = nl;
+      j = nh;
+    } else if (m == 0) {
+      i = 0;
+      j = 0;
+      r = sp0;
+    } else {
+      const dd target = mul_d(avg, (double)m) - B;
+      const int jlo = (m > nl) ? m - nl : 0;
+      const int jhi = (m < nh) ? m : nh;
+      const int qa = (jlo + G - 1) / G, qb = jhi / G;
+      int lo = qa - 1, hi = qb;
+      while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (le(QL[lane - mid] + QH[mid], target))
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      int ja, jb;
+      dd g;
+      if (lo >= qa) {
+        ja = lo * G;
+        jb = ja + G - 1;
+        g = QL[lane - lo] + QH[lo];
+      } else {
+        ja = jlo;
+        jb = qa * G - 1;
+        const dd sl = (jlo == 0) ? QL[lane] : QL[64];
+        const int q0 = ja / G;
+        dd sh = QH[q0];
+        for (int e = q0 * G; e < ja; ++e) sh = add_d(sh, Wv[ppos(nl + e)]);
+        g = sl + sh;
+      }
+      if (jb > jhi) jb = jhi;
+      int jj = ja;
+      while (jj < jb) {
+        const dd g2 = add_d(add_d(g, Wv[ppos(nl + jj)]), -Wv[ppos(m - jj - 1)]);
+        if (!le(g2, target)) break;
+        g = g2;
+        ++jj;
+      }
+      j = jj;
+      i = m - jj;
+      if (j0 + (uint64_t)j < H) r = (add_d(g, Wv[ppos(nl + j)]) + B) - mul_d(avg, (double)m);
+    }
   }
+  int ie = __shfl_down(i, 1, 64), je = __shfl_down(j, 1, 64);
+  if (lane == 63) {
+    ie = nl;
+    je = nh;
+  }
+
+  // 4. the sweep over this lane's rows
   while (i < ie || j < je) {
-    const uint64_t jj = j0 + (uint64_t)j;
+    const uint64_t jg = j0 + (uint64_t)j;
     if (j < je && (le(r, avg) || i == ie)) {
-      const uint32_t h = h_idx[jj];
-      const bool next = jj + 1 < H;
+      const uint32_t h = Ix[ppos(nl + j)];
+      const bool next = jg + 1 < H;
       prob[h] = clamp01(quot(r, avg));
-      alias[h] = next ? h_idx[jj + 1] : h;
-      if (next) r = add_d(r - avg, h_w[jj + 1]);
+      alias[h] = next ? Ix[ppos(nl + j + 1)] : h;
+      if (next) r = add_d(r - avg, Wv[ppos(nl + j + 1)]);
       ++j;
     } else {
-      const uint32_t l = l_idx[i0 + i];
-      if (jj < H) {
-        alias[l] = h_idx[jj];
-        r = r - add_d(avg, -l_w[i0 + i]);
+      if (jg < H) {
+        Ao[ppos(i)] = Ix[ppos(nl + j)];
+        r = r - add_d(avg, -Wv[ppos(i)]);
       } else {
-        alias[l] = l;
+        Ao[ppos(i)] = Ix[ppos(i)];
       }
       ++i;
     }
   }
+  wave_lds_sync();
+
+  // 5. light aliases, written in light (near item) order
+  for (int e = lane; e < nl; e += 64) alias[Ix[ppos(e)]] = Ao[ppos(e)];
 }
 
-// ---------------------------------------------------------------------------
-// Host launcher
-// ---------------------------------------------------------------------------
 // Largest dynamic LDS allocation one block may make on the current device
 // (queried once per device; the attribute query does not synchronise).
 static size_t device_max_lds_per_block() {
@@ -699,9 +727,8 @@ int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alia
   char *ws = (char *)d_ws;
   alias_ws_header *hdr = (alias_ws_header *)(ws + Lo.pub.header);
   ReducePart *parts = (ReducePart *)(ws + Lo.parts);
-  uint32_t *flags = (uint32_t *)(ws + Lo.flags);
-  TileWords *ta = (TileWords *)(ws + Lo.tile_a);
-  TileWords *tp = (TileWords *)(ws + Lo.tile_p);
+  TileSum *tsum = (TileSum *)(ws + Lo.tilesum);
+  TilePrefix *tpre = (TilePrefix *)(ws + Lo.tilepre);
   uint32_t *l_idx = (uint32_t *)(ws + Lo.pub.l_idx);
   uint32_t *h_idx = (uint32_t *)(ws + Lo.pub.h_idx);
   double *l_w = (double *)(ws + Lo.pub.l_w);
@@ -713,16 +740,19 @@ int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alia
   dd *spill = (dd *)(ws + Lo.pub.spill);
   const uint32_t tiles = Lo.pub.tiles, s = Lo.pub.sections, rb = Lo.pub.reduce_blocks;
 
-  hipLaunchKernelGGL(k_reduce, dim3(rb), dim3(kReduceThreads), 0, st, d_w, n, parts, flags, tiles);
+  hipLaunchKernelGGL(k_reduce, dim3(rb), dim3(kReduceThreads), 0, st, d_w, n, parts);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, parts, rb, n, hdr, agg_l, agg_h,
                      d_status);
-  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, flags, ta,
-                     tp, tiles, l_idx, l_w, h_idx, h_w, agg_l, agg_h, d_prob);
+  hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tsum, d_prob);
+  hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(kScanThreads), 0, st, tsum, tiles, n, hdr, tpre,
+                     agg_l, agg_h);
+  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tpre, l_idx,
+                     l_w, h_idx, h_w, agg_l, agg_h);
   hipLaunchKernelGGL(k_split, dim3((s + 1 + 255) / 256), dim3(256), 0, st, hdr, agg_l, agg_h, l_w,
                      h_w, s, Lo.chunk, n, sp_i, sp_j, spill, model, model_bytes,
                      &hdr->split_fallbacks);
   // one wave per section; as many waves per block as the LDS allows (<= 4)
-  const size_t per_wave = (size_t)(ppos((int)Lo.chunk + 3) + 1) * sizeof(dd);
+  const size_t per_wave = pack_lds(Lo.chunk).bytes;
   const size_t max_lds = device_max_lds_per_block();
   size_t waves = max_lds / per_wave;
   if (waves > (size_t)kPackWaves) waves = kPackWaves;

@@ -19,14 +19,18 @@ constexpr uint32_t kMinChunk = 64;
 constexpr uint32_t kMaxChunk = 2048;
 constexpr int kPackWaves = 4;            // sections per pack block (one wave each)
 
-// Published state of one partition tile for the decoupled look-back: the
-// number of light items and the light / heavy weight sums as signed 128-bit
-// fixed-point integers (value * 2^-fx_exp), each word stored separately.
-struct TileWords {
-  uint64_t cnt;
-  uint64_t sl_lo, sl_hi;
-  uint64_t sh_lo, sh_hi;
-  uint64_t pad[3];
+// Per-tile light count and light / heavy weight sums (4096-item tiles).
+struct TileSum {
+  uint32_t cnt;
+  uint32_t pad;
+  dd sl, sh;
+};
+
+// Exclusive prefix of TileSum over the tiles before a tile.
+struct TilePrefix {
+  uint64_t l_before;
+  uint64_t pad;
+  dd pl, ph;
 };
 
 struct ReducePart {
@@ -39,9 +43,8 @@ struct ReducePart {
 struct Layout {
   alias_ws_layout pub;
   uint64_t parts;      // ReducePart[reduce_blocks]
-  uint64_t flags;      // uint32 per tile
-  uint64_t tile_a;     // TileWords per tile: aggregate
-  uint64_t tile_p;     // TileWords per tile: inclusive prefix
+  uint64_t tilesum;    // TileSum per tile
+  uint64_t tilepre;    // TilePrefix per tile
   uint32_t chunk;
 };
 
@@ -72,9 +75,8 @@ inline bool compute_layout(uint64_t n, const alias_build_opts *o, Layout *L) {
   };
   L->pub.header = take(sizeof(alias_ws_header));
   L->parts = take(rb * sizeof(ReducePart));
-  L->flags = take(tiles * sizeof(uint32_t));
-  L->tile_a = take(tiles * sizeof(TileWords));
-  L->tile_p = take(tiles * sizeof(TileWords));
+  L->tilesum = take(tiles * sizeof(TileSum));
+  L->tilepre = take(tiles * sizeof(TilePrefix));
   L->pub.l_idx = take(n * 4);
   L->pub.h_idx = take(n * 4);
   L->pub.l_w = take(n * 8);
