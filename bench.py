@@ -22,9 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of the build per item: read w twice (16), write the
-# light/heavy lists with weights (12), read them in the pack (12), write the
-# table row (8 + 4)
+# algorithmic bytes of the build per item: read w twice (16: total weight,
+# then partition), write the light/heavy lists with weights (12), read them in
+# the pack (12), write the table row (8 + 4)
 BUILD_BYTES_PER_ITEM = 52
 
 
@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="powerlaw_2p27")
     ap.add_argument("--draws", type=int, default=None)
+    ap.add_argument("--layout", choices=["rows", "soa"], default="rows",
+                    help="table as 16-byte rows (one gather per draw) or two arrays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=None,
                     help="items in the CPU oracle's build sample (default: the workload's n)")
@@ -106,18 +108,29 @@ def main():
     w = torch.from_numpy(w_host).to(dev)
     del w_host
     builder = pkg.Builder(n, chunk=chunk, device=dev)
-    prob = torch.empty(n, dtype=torch.float64, device=dev)
-    alias = torch.empty(n, dtype=torch.int32, device=dev)
+    rows_layout = args.layout == "rows"
+    if rows_layout:
+        rows = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        prob, alias = pkg.rows_split(rows)
+    else:
+        prob = torch.empty(n, dtype=torch.float64, device=dev)
+        alias = torch.empty(n, dtype=torch.int32, device=dev)
     out = torch.empty(draws, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
     def step(events=None):
         if events:
             events[0].record(stream)
-        builder.build(w, prob, alias, stream=stream)
+        if rows_layout:
+            builder.build_rows(w, rows, stream=stream)
+        else:
+            builder.build(w, prob, alias, stream=stream)
         if events:
             events[1].record(stream)
-        pkg.sample(prob, alias, draws, inputs.SAMPLE_SEED, out=out, stream=stream)
+        if rows_layout:
+            pkg.sample_rows(rows, draws, inputs.SAMPLE_SEED, out=out, stream=stream)
+        else:
+            pkg.sample(prob, alias, draws, inputs.SAMPLE_SEED, out=out, stream=stream)
         if events:
             events[2].record(stream)
 
@@ -143,17 +156,20 @@ def main():
     print(f"[bench] timed {args.steps} steps: build {b_ms:.3f} ms, sample {s_ms:.3f} ms",
           file=sys.stderr, flush=True)
 
-    # expected fraction of draws that read the alias column: mean(1 - prob)
+    # expected fraction of draws that take the alias: mean(1 - prob)
     p_alias = float((1.0 - prob).mean().item())
-    sample_bytes = draws * (4 + 8 + 4 * p_alias)
+    # algorithmic bytes per draw: the output word plus the row fields read
+    per_draw = (4 + 16) if rows_layout else (4 + 8 + 4 * p_alias)
+    sample_bytes = draws * per_draw
     sample_gbs = sample_bytes / (s_ms * 1e-3) / 1e9
     build_gbs = n * BUILD_BYTES_PER_ITEM / (b_ms * 1e-3) / 1e9
     if s_ms >= b_ms:
         roof = {"bound": "hbm", "achieved": round(sample_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(sample_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sample",
+                "kernel": "k_sample_rows" if rows_layout else "k_sample",
                 "bytes_per_launch": round(sample_bytes),
-                "bytes_model": "per draw: 4 B out + 8 B prob + 4 B alias x P(alias)",
+                "bytes_model": ("per draw: 4 B out + one 16 B row" if rows_layout else
+                                "per draw: 4 B out + 8 B prob + 4 B alias x P(alias)"),
                 "p_alias": round(p_alias, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(build_gbs, 1), "peak": HBM_PEAK_GBS,
@@ -177,7 +193,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dist": cfg["dist"],
                    "alpha": cfg.get("alpha"), "chunk": chunk, "split": "binary",
-                   "draws": draws, "parallelism": "none (1 GPU)"},
+                   "draws": draws, "layout": args.layout, "parallelism": "none (1 GPU)"},
         "build_ms": b_ms,
         "build_hbm_frac": round(build_gbs / HBM_PEAK_GBS, 4),
         "build_gbs": round(build_gbs, 1),

@@ -134,6 +134,15 @@ int alias_workspace_layout(uint64_t n, const alias_build_opts *opts, alias_ws_la
 int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
                 size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts, void *stream);
 
+/* Same construction, table written as n 16-byte rows
+ *   struct { double prob; uint32_t alias; uint32_t reserved; }
+ * so that a draw reads one row with one 128-bit access (the paper's 128-bit
+ * table rows, Sec. 6 "Implementation details").  d_rows: device, n*16
+ * bytes, 16-byte aligned.  Other arguments, results and errors as in
+ * alias_build; every row's reserved word is written as 0. */
+int alias_build_rows(const double *d_w, uint64_t n, void *d_rows, void *d_ws, size_t ws_bytes,
+                     int32_t *d_status, const alias_build_opts *opts, void *stream);
+
 /* Draw `count` samples with replacement from a table (Sec. 2.2 Walker draw;
  * Sec. 5 baseline sampling: one draw per thread).
  * Draw t (t = first_draw .. first_draw+count-1) takes one Philox4x32-10 block
@@ -149,6 +158,12 @@ int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias
 int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint64_t count,
                  uint64_t seed, uint64_t first_draw, uint32_t table_id, uint32_t *d_out,
                  void *stream);
+
+/* alias_sample for a table of 16-byte rows (as written by alias_build_rows):
+ * the same draws, bit for bit, as alias_sample on the equivalent two-array
+ * table.  d_rows: device, n rows, 16-byte aligned. */
+int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
+                      uint64_t first_draw, uint32_t table_id, uint32_t *d_out, void *stream);
 
 /* Human-readable text of a status code (static string). */
 const char *alias_status_str(int code);

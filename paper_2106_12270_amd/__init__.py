@@ -11,7 +11,8 @@ import os
 
 __all__ = [
     "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
-    "sample", "Builder", "status_str", "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
+    "sample", "build_rows", "sample_rows", "rows_split", "Builder", "status_str",
+    "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
     "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
 ]
 
@@ -78,6 +79,10 @@ def lib():
         L.alias_build.restype = C.c_int
         L.alias_sample.argtypes = [vp, vp, u64, u64, u64, u64, u32, vp, vp]
         L.alias_sample.restype = C.c_int
+        L.alias_build_rows.argtypes = [vp, u64, vp, vp, C.c_size_t, vp, C.POINTER(BuildOpts), vp]
+        L.alias_build_rows.restype = C.c_int
+        L.alias_sample_rows.argtypes = [vp, u64, u64, u64, u64, u32, vp, vp]
+        L.alias_sample_rows.restype = C.c_int
         L.alias_status_str.argtypes = [C.c_int]
         L.alias_status_str.restype = C.c_char_p
         L.alias_version.argtypes = []
@@ -181,6 +186,25 @@ class Builder:
             raise AliasError(st, "alias_build")
         return prob, alias
 
+    def build_rows(self, w, rows=None, stream=None):
+        """Build into 16-byte rows: an int32 tensor of shape (n, 4) whose row
+        k holds prob[k] (float64 in words 0-1) and alias[k] (word 2)."""
+        import torch
+
+        _check_dev(w, torch.float64, "w")
+        if w.numel() != self.n:
+            raise ValueError("w has the wrong length for this builder")
+        if rows is None:
+            rows = torch.empty((self.n, 4), dtype=torch.int32, device=w.device)
+        _check_rows(rows, self.n)
+        st = lib().alias_build_rows(C.c_void_p(w.data_ptr()), self.n, C.c_void_p(rows.data_ptr()),
+                                    C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                    C.c_void_p(self.status.data_ptr()), C.byref(self.opts),
+                                    _stream(stream))
+        if st:
+            raise AliasError(st, "alias_build_rows")
+        return rows
+
     # --- inspection of the last build (reads device memory; synchronises) ---
     def _view(self, off, count, dtype):
         import torch
@@ -216,6 +240,21 @@ class Builder:
         return out
 
 
+def _check_rows(rows, n):
+    import torch
+
+    _check_dev(rows, torch.int32, "rows")
+    if rows.dim() != 2 or rows.shape[1] != 4 or rows.shape[0] < n:
+        raise TypeError("rows must be an int32 tensor of shape (n, 4)")
+    if rows.data_ptr() % 16:
+        raise TypeError("rows must be 16-byte aligned")
+
+
+def rows_split(rows):
+    """Views (prob float64, alias int32) of a 16-byte-row table."""
+    return rows.view(__import__("torch").float64)[:, 0], rows[:, 2]
+
+
 def build(w, chunk=None, split="binary", model=None, stream=None, check=True):
     """Build the alias table of a float64 CUDA tensor.  Returns (prob, alias)
     with alias as int32 (bit pattern of the uint32 ids).  With check=True the
@@ -227,6 +266,36 @@ def build(w, chunk=None, split="binary", model=None, stream=None, check=True):
         if st:
             raise AliasError(st, "alias_build")
     return prob, alias
+
+
+def build_rows(w, chunk=None, split="binary", model=None, stream=None, check=True):
+    """Build the table as 16-byte rows (int32 tensor of shape (n, 4))."""
+    b = Builder(w.numel(), chunk, split, model, device=w.device)
+    rows = b.build_rows(w, stream=stream)
+    if check:
+        st = int(b.status.item())
+        if st:
+            raise AliasError(st, "alias_build_rows")
+    return rows
+
+
+def sample_rows(rows, count, seed, first_draw=0, table_id=0, out=None, stream=None):
+    """Draw `count` samples from a 16-byte-row table (same draws as sample())."""
+    import torch
+
+    n = rows.shape[0]
+    _check_rows(rows, n)
+    if out is None:
+        out = torch.empty(int(count), dtype=torch.int32, device=rows.device)
+    _check_dev(out, torch.int32, "out")
+    if out.numel() < count:
+        raise ValueError("out is too small")
+    st = lib().alias_sample_rows(C.c_void_p(rows.data_ptr()), n, int(count),
+                                 int(seed) & (2**64 - 1), int(first_draw), int(table_id),
+                                 C.c_void_p(out.data_ptr()), _stream(stream))
+    if st:
+        raise AliasError(st, "alias_sample_rows")
+    return out
 
 
 def sample(prob, alias, count, seed, first_draw=0, table_id=0, out=None, stream=None):

@@ -9,11 +9,13 @@
 #include "learned.hpp"
 
 namespace amdalias {
-int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
-                 int32_t *d_status, const Layout &Lo, const SplitModel *model, uint64_t model_bytes,
-                 hipStream_t st);
+int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias,
+                 TableRow *d_rows, void *d_ws, int32_t *d_status, const Layout &Lo,
+                 const SplitModel *model, uint64_t model_bytes, hipStream_t st);
 int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
                   uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st);
+int launch_sample_rows(const TableRow *rows, uint64_t n, uint64_t count, uint64_t seed,
+                       uint64_t first, uint32_t table, uint32_t *out, hipStream_t st);
 }  // namespace amdalias
 
 using namespace amdalias;
@@ -36,25 +38,47 @@ int alias_workspace_layout(uint64_t n, const alias_build_opts *opts, alias_ws_la
   return ALIAS_OK;
 }
 
-int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
-                size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts, void *stream) {
-  Layout L;
-  if (!d_w || !d_prob || !d_alias || !d_ws || !d_status) return ALIAS_EINVAL;
-  if (!aligned(d_w, 8) || !aligned(d_prob, 8) || !aligned(d_alias, 4) || !aligned(d_ws, 256) ||
-      !aligned(d_status, 4))
-    return ALIAS_EINVAL;
-  if (!compute_layout(n, opts, &L)) return ALIAS_EINVAL;
-  if (ws_bytes < L.pub.total_bytes) return ALIAS_EWORKSPACE;
-  const SplitModel *model = nullptr;
-  uint64_t model_bytes = 0;
+// Shared argument checks of the two build entry points.
+static int build_common(const double *d_w, uint64_t n, void *d_ws, size_t ws_bytes,
+                        int32_t *d_status, const alias_build_opts *opts, Layout *L,
+                        const SplitModel **model, uint64_t *model_bytes) {
+  if (!d_w || !d_ws || !d_status) return ALIAS_EINVAL;
+  if (!aligned(d_w, 8) || !aligned(d_ws, 256) || !aligned(d_status, 4)) return ALIAS_EINVAL;
+  if (!compute_layout(n, opts, L)) return ALIAS_EINVAL;
+  if (ws_bytes < L->pub.total_bytes) return ALIAS_EWORKSPACE;
+  *model = nullptr;
+  *model_bytes = 0;
   if (opts && opts->split_method == ALIAS_SPLIT_LEARNED) {
     if (!opts->split_model || opts->split_model_bytes < 16 || !aligned(opts->split_model, 4))
       return ALIAS_EMODEL;
-    model = (const SplitModel *)opts->split_model;
-    model_bytes = opts->split_model_bytes;
+    *model = (const SplitModel *)opts->split_model;
+    *model_bytes = opts->split_model_bytes;
   }
-  return launch_build(d_w, n, d_prob, d_alias, d_ws, d_status, L, model, model_bytes,
+  return ALIAS_OK;
+}
+
+int alias_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
+                size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts, void *stream) {
+  Layout L;
+  const SplitModel *model;
+  uint64_t model_bytes;
+  if (!d_prob || !d_alias || !aligned(d_prob, 8) || !aligned(d_alias, 4)) return ALIAS_EINVAL;
+  const int st = build_common(d_w, n, d_ws, ws_bytes, d_status, opts, &L, &model, &model_bytes);
+  if (st) return st;
+  return launch_build(d_w, n, d_prob, d_alias, nullptr, d_ws, d_status, L, model, model_bytes,
                       (hipStream_t)stream);
+}
+
+int alias_build_rows(const double *d_w, uint64_t n, void *d_rows, void *d_ws, size_t ws_bytes,
+                     int32_t *d_status, const alias_build_opts *opts, void *stream) {
+  Layout L;
+  const SplitModel *model;
+  uint64_t model_bytes;
+  if (!d_rows || !aligned(d_rows, 16)) return ALIAS_EINVAL;
+  const int st = build_common(d_w, n, d_ws, ws_bytes, d_status, opts, &L, &model, &model_bytes);
+  if (st) return st;
+  return launch_build(d_w, n, nullptr, nullptr, (TableRow *)d_rows, d_ws, d_status, L, model,
+                      model_bytes, (hipStream_t)stream);
 }
 
 int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint64_t count,
@@ -67,6 +91,16 @@ int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint
   if (first_draw + count < first_draw) return ALIAS_EINVAL;  // counter range wraps
   return launch_sample(d_prob, d_alias, n, count, seed, first_draw, table_id, d_out,
                        (hipStream_t)stream);
+}
+
+int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
+                      uint64_t first_draw, uint32_t table_id, uint32_t *d_out, void *stream) {
+  if (n == 0 || n > 0xFFFFFFFFull) return ALIAS_EINVAL;
+  if (count == 0) return ALIAS_OK;
+  if (!d_rows || !d_out || !aligned(d_rows, 16) || !aligned(d_out, 4)) return ALIAS_EINVAL;
+  if (first_draw + count < first_draw) return ALIAS_EINVAL;
+  return launch_sample_rows((const TableRow *)d_rows, n, count, seed, first_draw, table_id, d_out,
+                            (hipStream_t)stream);
 }
 
 const char *alias_status_str(int code) {

@@ -4,9 +4,8 @@
 // Pipeline, one stream, no host synchronisation or readback:
 //   k_reduce    per-block double-double sums of the weights + validation.
 //   k_finalize  W, W/N, status; resets the counters the later kernels use.
-//   k_tilesum   per 4096-item tile: light count, light and heavy weight sums;
-//               writes each item's own-row share w/avg (final for lights).
-//   k_tilescan  exclusive prefix over the tiles (one block, fixed order).
+//   k_tilesum   per 4096-item tile: light count, light and heavy weight sums.
+//   k_tilescan, k_groupscan  exclusive prefix over the tiles in two levels.
 //   k_partition stable light/heavy partition in item order with the tile
 //               offsets known; entries carry their weight (Sec. 4.2 "Weight
 //               in l and h Arrays"); prefix sums of the light / heavy weights
@@ -123,13 +122,11 @@ __global__ __launch_bounds__(256) void k_finalize(const ReducePart *__restrict__
 
 // ---------------------------------------------------------------------------
 // k_tilesum: per tile of 4096 items, the number of light items and the light
-// and heavy weight sums; also writes every item's own-row share w/avg (final
-// for light items, rewritten by k_pack for heavy ones).
+// and heavy weight sums.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_tilesum(const double *__restrict__ w, uint64_t n,
                                                           const alias_ws_header *hdr,
-                                                          TileSum *__restrict__ sums,
-                                                          double *__restrict__ prob) {
+                                                          TileSum *__restrict__ sums) {
   __shared__ dd s_l[kTileThreads / 64], s_h[kTileThreads / 64];
   __shared__ uint32_t s_c[kTileThreads / 64];
   if (hdr->status != ALIAS_OK) return;
@@ -144,7 +141,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(const double *__restri
     if (gi < n) {
       const double x = w[gi];
       const bool light = le(dd_make(x, 0.0), avg);
-      prob[gi] = clamp01(quot(dd_make(x, 0.0), avg));
       dd a = light ? acc_l : acc_h;
       a = add_d(a, x);
       if (light)
@@ -181,89 +177,139 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// k_tilescan: exclusive prefix over the tiles (one block, fixed order), the
-// totals, and the final prefix-sum points when a list length is a multiple
-// of the aggregate stride.
+// Tile scan in two levels, fixed combination order throughout:
+//   k_tilescan   one block per group of 1024 tiles: exclusive prefix of the
+//                tile sums within the group, and the group total;
+//   k_groupscan  one block: exclusive prefix over the groups, the totals, and
+//                the final prefix-sum points when a list length is a
+//                multiple of the aggregate stride.
 // ---------------------------------------------------------------------------
-constexpr int kScanThreads = 1024;
+struct ScanVal {
+  uint64_t c;
+  dd l, h;
+};
 
-__global__ __launch_bounds__(kScanThreads) void k_tilescan(const TileSum *__restrict__ sums,
-                                                           uint32_t tiles, uint64_t n,
-                                                           alias_ws_header *hdr,
-                                                           TilePrefix *__restrict__ pre,
-                                                           dd *__restrict__ agg_l,
-                                                           dd *__restrict__ agg_h) {
-  __shared__ dd s_l[kScanThreads / 64], s_h[kScanThreads / 64];
-  __shared__ uint64_t s_c[kScanThreads / 64];
-  if (hdr->status != ALIAS_OK) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t per = (tiles + kScanThreads - 1) / kScanThreads;
-  const uint32_t b = tid * per;
-  const uint32_t e = (b + per < tiles) ? b + per : tiles;
-  dd sl = dd_make(0.0, 0.0), sh = dd_make(0.0, 0.0);
-  uint64_t c = 0;
-  for (uint32_t t = b; t < e; ++t) {
-    sl = sl + sums[t].sl;
-    sh = sh + sums[t].sh;
-    c += sums[t].cnt;
-  }
-  // block exclusive scan of (c, sl, sh)
-  dd il = wave_inclusive_scan(sl, lane), ih = wave_inclusive_scan(sh, lane);
-  uint64_t ic = c;
+__device__ __forceinline__ ScanVal sv_add(const ScanVal &a, const ScanVal &b) {
+  ScanVal r;
+  r.c = a.c + b.c;
+  r.l = a.l + b.l;
+  r.h = a.h + b.h;
+  return r;
+}
+
+// exclusive scan over a 1024-thread block; *total gets the block total
+__device__ __forceinline__ ScanVal block_exscan_1024(ScanVal v, ScanVal *s_w /*[16]*/,
+                                                     ScanVal *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ScanVal inc;
+  inc.l = wave_inclusive_scan(v.l, lane);
+  inc.h = wave_inclusive_scan(v.h, lane);
+  inc.c = v.c;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    uint64_t o = __shfl_up(ic, d, 64);
-    if (lane >= d) ic += o;
+    uint64_t o = __shfl_up(inc.c, d, 64);
+    if (lane >= d) inc.c += o;
   }
-  if (lane == 63) {
-    s_l[wave] = il;
-    s_h[wave] = ih;
-    s_c[wave] = ic;
+  if (lane == 63) s_w[wave] = inc;
+  ScanVal ex;
+  ex.l = shfl_up(inc.l, 1);
+  ex.h = shfl_up(inc.h, 1);
+  ex.c = __shfl_up(inc.c, 1, 64);
+  if (lane == 0) {
+    ex.c = 0;
+    ex.l = dd_make(0.0, 0.0);
+    ex.h = dd_make(0.0, 0.0);
   }
   __syncthreads();
-  dd ol = dd_make(0.0, 0.0), oh = dd_make(0.0, 0.0);
-  uint64_t oc = 0;
-  dd tl = dd_make(0.0, 0.0), th = dd_make(0.0, 0.0);
-  uint64_t tc = 0;
-  for (int k = 0; k < kScanThreads / 64; ++k) {
-    if (k < wave) {
-      ol = ol + s_l[k];
-      oh = oh + s_h[k];
-      oc += s_c[k];
-    }
-    tl = tl + s_l[k];
-    th = th + s_h[k];
-    tc += s_c[k];
+  ScanVal off;
+  off.c = 0;
+  off.l = dd_make(0.0, 0.0);
+  off.h = dd_make(0.0, 0.0);
+  ScanVal tot = off;
+  for (int k = 0; k < 16; ++k) {
+    if (k < wave) off = sv_add(off, s_w[k]);
+    tot = sv_add(tot, s_w[k]);
   }
-  dd xl = shfl_up(il, 1), xh = shfl_up(ih, 1);
-  uint64_t xc = __shfl_up(ic, 1, 64);
-  if (lane == 0) {
-    xl = dd_make(0.0, 0.0);
-    xh = dd_make(0.0, 0.0);
-    xc = 0;
+  *total = tot;
+  return sv_add(off, ex);
+}
+
+__global__ __launch_bounds__(kScanGroup) void k_tilescan(const TileSum *__restrict__ sums,
+                                                         uint32_t tiles, const alias_ws_header *hdr,
+                                                         TilePrefix *__restrict__ pre,
+                                                         TileSum *__restrict__ grp) {
+  __shared__ ScanVal s_w[16];
+  if (hdr->status != ALIAS_OK) return;
+  const uint32_t t = blockIdx.x * kScanGroup + threadIdx.x;
+  ScanVal v;
+  v.c = 0;
+  v.l = dd_make(0.0, 0.0);
+  v.h = dd_make(0.0, 0.0);
+  if (t < tiles) {
+    const TileSum ts = sums[t];
+    v.c = ts.cnt;
+    v.l = ts.sl;
+    v.h = ts.sh;
   }
-  dd rl = ol + xl, rh = oh + xh;
-  uint64_t rc = oc + xc;
-  for (uint32_t t = b; t < e; ++t) {
+  ScanVal tot;
+  const ScanVal ex = block_exscan_1024(v, s_w, &tot);
+  if (t < tiles) {
     TilePrefix p;
-    p.l_before = rc;
-    p.pl = rl;
-    p.ph = rh;
+    p.l_before = ex.c;
+    p.pad = 0;
+    p.pl = ex.l;
+    p.ph = ex.h;
     pre[t] = p;
-    rl = rl + sums[t].sl;
-    rh = rh + sums[t].sh;
-    rc += sums[t].cnt;
   }
-  if (tid == 0) {
-    const uint64_t L = tc, H = n - tc;
+  if (threadIdx.x == 0) {
+    TileSum g;
+    g.cnt = (uint32_t)tot.c;
+    g.pad = 0;
+    g.sl = tot.l;
+    g.sh = tot.h;
+    grp[blockIdx.x] = g;
+  }
+}
+
+__global__ __launch_bounds__(kScanGroup) void k_groupscan(const TileSum *__restrict__ grp,
+                                                          uint32_t groups, uint64_t n,
+                                                          alias_ws_header *hdr,
+                                                          TilePrefix *__restrict__ gpre,
+                                                          dd *__restrict__ agg_l,
+                                                          dd *__restrict__ agg_h) {
+  __shared__ ScanVal s_w[16];
+  if (hdr->status != ALIAS_OK) return;
+  const uint32_t g = threadIdx.x;
+  ScanVal v;
+  v.c = 0;
+  v.l = dd_make(0.0, 0.0);
+  v.h = dd_make(0.0, 0.0);
+  if (g < groups) {
+    const TileSum ts = grp[g];
+    v.c = ts.cnt;
+    v.l = ts.sl;
+    v.h = ts.sh;
+  }
+  ScanVal tot;
+  const ScanVal ex = block_exscan_1024(v, s_w, &tot);
+  if (g < groups) {
+    TilePrefix p;
+    p.l_before = ex.c;
+    p.pad = 0;
+    p.pl = ex.l;
+    p.ph = ex.h;
+    gpre[g] = p;
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t L = tot.c, H = n - tot.c;
     hdr->L = L;
     hdr->H = H;
-    hdr->sl_hi = tl.hi;
-    hdr->sl_lo = tl.lo;
-    hdr->sh_hi = th.hi;
-    hdr->sh_lo = th.lo;
-    if ((L & (kAggStride - 1)) == 0) agg_l[L / kAggStride] = tl;
-    if ((H & (kAggStride - 1)) == 0) agg_h[H / kAggStride] = th;
+    hdr->sl_hi = tot.l.hi;
+    hdr->sl_lo = tot.l.lo;
+    hdr->sh_hi = tot.h.hi;
+    hdr->sh_lo = tot.h.lo;
+    if ((L & (kAggStride - 1)) == 0) agg_l[L / kAggStride] = tot.l;
+    if ((H & (kAggStride - 1)) == 0) agg_h[H / kAggStride] = tot.h;
   }
 }
 
@@ -281,7 +327,8 @@ __device__ __forceinline__ int spos(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(kTileThreads) void k_partition(
     const double *__restrict__ w, uint64_t n, const alias_ws_header *hdr,
-    const TilePrefix *__restrict__ pre, uint32_t *__restrict__ l_idx, double *__restrict__ l_w,
+    const TilePrefix *__restrict__ pre, const TilePrefix *__restrict__ gpre,
+    uint32_t *__restrict__ l_idx, double *__restrict__ l_w,
     uint32_t *__restrict__ h_idx, double *__restrict__ h_w, dd *__restrict__ agg_l,
     dd *__restrict__ agg_h) {
   __shared__ PartShared S;
@@ -362,11 +409,11 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(
     sl_lane = dd_make(0.0, 0.0);
     sh_lane = dd_make(0.0, 0.0);
   }
-  const TilePrefix tp = pre[tile];
-  const uint64_t l_before = tp.l_before;
+  const TilePrefix tp = pre[tile], gp = gpre[tile / kScanGroup];
+  const uint64_t l_before = gp.l_before + tp.l_before;
   const uint64_t h_before = base - l_before;
-  const dd pl_thr = tp.pl + (sl_off + sl_lane);
-  const dd ph_thr = tp.ph + (sh_off + sh_lane);
+  const dd pl_thr = (gp.pl + tp.pl) + (sl_off + sl_lane);
+  const dd ph_thr = (gp.ph + tp.ph) + (sh_off + sh_lane);
   uint32_t rl = cl_off + cl_inc - nl;
   uint32_t rh = Lt + ch_off + ch_inc - nh;
 
@@ -524,37 +571,98 @@ __global__ __launch_bounds__(256) void k_split(const alias_ws_header *hdr, const
 }
 
 // ---------------------------------------------------------------------------
-// k_pack: one wave per section of C rows (Sec. 4.2).  The section's light
-// and heavy entries (weights and ids) are staged in LDS with coalesced loads
-// (the paper's shared-memory pack), prefix sums are formed every G = C/64
-// entries, each lane finds its start state at local row G*lane by a search
-// on those sums and a walk of at most G entries, then sweeps its G rows
-// reading only LDS.  Light aliases are staged and written out in light order.
+// k_pack: one wave per section of C rows (Sec. 4.2).
+//   1. stage the section's light and heavy entries (weight, id) in LDS with
+//      coalesced loads (the paper's shared-memory pack with weights in l/h);
+//   2. prefix sums every S = min(16, C/64) entries of both lists;
+//   3. each lane finds its start state at local row G*lane (G = C/64) by a
+//      search on those sums and a walk of fewer than S entries;
+//   4. each lane sweeps its G rows in LDS: a light row records its alias, a
+//      closing heavy records the light index at which it closed; the
+//      residual advances by (incoming weight - W/N) either way;
+//   5. heavy rows are finished in parallel: residual at closing from the
+//      prefix sums, prob = residual / (W/N), alias = next heavy;
+//   6. light rows are written in light (near item) order: prob = w / (W/N)
+//      and the recorded alias.  Every table row is written exactly once.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int ppos(int e) { return e + (e >> 4); }  // padded LDS index
 
 struct PackLds {
-  uint32_t w_off, ix_off, ao_off, q_off, bytes;
+  uint32_t w_off, q_off, ix_off, ao_off, bytes, nq;
 };
+
+__host__ __device__ inline int pack_stride(uint32_t chunk) {
+  const int G = (int)(chunk >> 6);
+  return G < 16 ? G : 16;
+}
 
 __host__ __device__ inline PackLds pack_lds(uint32_t chunk) {
   PackLds p;
   const uint32_t nw = (uint32_t)ppos((int)chunk + 2) + 1;
-  const uint32_t na = (uint32_t)ppos((int)chunk) + 1;
+  p.nq = chunk / (uint32_t)pack_stride(chunk) + 2;
   p.w_off = 0;
   p.q_off = (8u * nw + 15u) & ~15u;
-  p.ix_off = p.q_off + 16u * 2u * 66u;
+  p.ix_off = p.q_off + 16u * 2u * p.nq;
   p.ao_off = p.ix_off + 4u * nw;
-  p.bytes = (p.ao_off + 4u * na + 15u) & ~15u;
+  p.bytes = (p.ao_off + 4u * nw + 15u) & ~15u;
   return p;
 }
 
+// Prefix sums every S entries of one staged list: Q[q] = sum of the first
+// min(q*S, cnt) entries, for q = 0 .. C/S.  Lane t owns entries [tG, tG+G).
+__device__ __forceinline__ void pack_prefix(const double *Wv, int off, int cnt, dd *Q, int G,
+                                            int S, int lane) {
+  const int b = lane * G;
+  dd acc = dd_make(0.0, 0.0);
+  dd part[2];  // partial sums at the lane's stride points (G/S <= 2)
+  const int per = G / S;
+  for (int u = 0; u < G; ++u) {
+    if ((u % S) == 0 && (u / S) < 2) part[u / S] = acc;
+    if (b + u < cnt) acc = add_d(acc, Wv[ppos(off + b + u)]);
+  }
+  const dd inc = wave_inclusive_scan(acc, lane);
+  dd ex = shfl_up(inc, 1);
+  if (lane == 0) ex = dd_make(0.0, 0.0);
+  for (int k = 0; k < per && k < 2; ++k) Q[(b / S) + k] = ex + part[k];
+  if (lane == 63) Q[(64 * G) / S] = inc;
+}
+
+// sigma of the first p entries of a staged list, from the stride points and
+// fewer than S entries.
+__device__ __forceinline__ dd pack_sigma(const double *Wv, int off, const dd *Q, int S, int p) {
+  const int q = p / S;
+  dd sgm = Q[q];
+  for (int e = q * S; e < p; ++e) sgm = add_d(sgm, Wv[ppos(off + e)]);
+  return sgm;
+}
+
+// Table output: two arrays (prob, alias) or one array of 16-byte rows.
+struct TableOut {
+  double *prob;
+  uint32_t *alias;
+  TableRow *rows;
+};
+
+template <bool kRows>
+__device__ __forceinline__ void put_row(const TableOut &t, uint32_t item, double p, uint32_t a) {
+  if (kRows) {
+    TableRow r;
+    r.prob = p;
+    r.alias = a;
+    r.pad = 0u;
+    t.rows[item] = r;
+  } else {
+    t.prob[item] = p;
+    t.alias[item] = a;
+  }
+}
+
+template <bool kRows>
 __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     const alias_ws_header *hdr, const uint32_t *__restrict__ l_idx, const double *__restrict__ l_w,
     const uint32_t *__restrict__ h_idx, const double *__restrict__ h_w,
     const uint32_t *__restrict__ split_i, const uint32_t *__restrict__ split_j,
-    const dd *__restrict__ spill, uint32_t s, uint32_t chunk, double *__restrict__ prob,
-    uint32_t *__restrict__ alias, int32_t *d_status) {
+    const dd *__restrict__ spill, uint32_t s, uint32_t chunk, TableOut out, int32_t *d_status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t k = blockIdx.x * (blockDim.x >> 6) + wave;
@@ -563,7 +671,7 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
   unsigned char *base = smem_raw + (size_t)wave * PLy.bytes;
   double *Wv = (double *)(base + PLy.w_off);
   dd *QL = (dd *)(base + PLy.q_off);
-  dd *QH = QL + 66;
+  dd *QH = QL + PLy.nq;
   uint32_t *Ix = (uint32_t *)(base + PLy.ix_off);
   uint32_t *Ao = (uint32_t *)(base + PLy.ao_off);
 
@@ -577,17 +685,19 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     if (lane == 0) *d_status = ALIAS_EINTERNAL;
     return;
   }
+  const Divisor dv = make_divisor(avg);
   if (j0 >= H) {  // no heavy item left: remaining lights keep their whole row
     for (int e = lane; e < nl; e += 64) {
       const uint32_t l = l_idx[i0 + e];
-      alias[l] = l;
+      put_row<kRows>(out, l, clamp01(quot_fast(dd_make(l_w[i0 + e], 0.0), dv)), l);
     }
     return;
   }
   const int nhl = (nh + 1 < (int)(H - j0)) ? nh + 1 : (int)(H - j0);
-  const int G = (int)(chunk >> 6);  // rows per lane == prefix-sum stride
+  const int G = (int)(chunk >> 6);  // rows per lane
+  const int S = pack_stride(chunk);  // prefix-sum stride
 
-  // 1. stage the section's lights (slots 0..nl-1) and heavies (nl..nl+nhl-1)
+  // 1. stage lights in slots [0, nl), heavies in [nl, nl + nhl)
   for (int e = lane; e < nl; e += 64) {
     Wv[ppos(e)] = l_w[i0 + e];
     Ix[ppos(e)] = l_idx[i0 + e];
@@ -598,26 +708,13 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
   }
   wave_lds_sync();
 
-  // 2. prefix sums every G entries: QL[q] = sum of the first min(qG, nl) lights
-  {
-    dd al = dd_make(0.0, 0.0), ah = dd_make(0.0, 0.0);
-    const int b = lane * G;
-    for (int u = 0; u < G; ++u) {
-      if (b + u < nl) al = add_d(al, Wv[ppos(b + u)]);
-      if (b + u < nhl) ah = add_d(ah, Wv[ppos(nl + b + u)]);
-    }
-    const dd il = wave_inclusive_scan(al, lane), ih = wave_inclusive_scan(ah, lane);
-    QL[lane + 1] = il;
-    QH[lane + 1] = ih;
-    if (lane == 0) {
-      QL[0] = dd_make(0.0, 0.0);
-      QH[0] = dd_make(0.0, 0.0);
-    }
-  }
+  // 2. prefix sums every S entries
+  pack_prefix(Wv, 0, nl, QL, G, S, lane);
+  pack_prefix(Wv, nl, nhl, QH, G, S, lane);
   wave_lds_sync();
 
   const dd sp0 = spill[k];
-  const dd B = sp0 - dd_make(Wv[ppos(nl)], 0.0);  // f_local(i, j) + B - m*avg = global f - m*avg
+  const dd B = sp0 - dd_make(Wv[ppos(nl)], 0.0);  // local f(i, j) + B - m*avg = global f - m*avg
   const int total = nl + nh;
 
   // 3. this lane's start state at local row m = G*lane
@@ -636,11 +733,12 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
       const dd target = mul_d(avg, (double)m) - B;
       const int jlo = (m > nl) ? m - nl : 0;
       const int jhi = (m < nh) ? m : nh;
-      const int qa = (jlo + G - 1) / G, qb = jhi / G;
+      const int qa = (jlo + S - 1) / S, qb = jhi / S;
+      const int mq = m / S;
       int lo = qa - 1, hi = qb;
       while (lo < hi) {
         const int mid = lo + (hi - lo + 1) / 2;
-        if (le(QL[lane - mid] + QH[mid], target))
+        if (le(QL[mq - mid] + QH[mid], target))
           lo = mid;
         else
           hi = mid - 1;
@@ -648,17 +746,13 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
       int ja, jb;
       dd g;
       if (lo >= qa) {
-        ja = lo * G;
-        jb = ja + G - 1;
-        g = QL[lane - lo] + QH[lo];
+        ja = lo * S;
+        jb = ja + S - 1;
+        g = QL[mq - lo] + QH[lo];
       } else {
         ja = jlo;
-        jb = qa * G - 1;
-        const dd sl = (jlo == 0) ? QL[lane] : QL[64];
-        const int q0 = ja / G;
-        dd sh = QH[q0];
-        for (int e = q0 * G; e < ja; ++e) sh = add_d(sh, Wv[ppos(nl + e)]);
-        g = sl + sh;
+        jb = qa * S - 1;
+        g = pack_sigma(Wv, 0, QL, S, m - jlo) + pack_sigma(Wv, nl, QH, S, jlo);
       }
       if (jb > jhi) jb = jhi;
       int jj = ja;
@@ -679,30 +773,39 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
     je = nh;
   }
 
-  // 4. the sweep over this lane's rows
+  // 4. the sweep: lights record their alias, closing heavies their light index
+  const dd navg = -avg;
   while (i < ie || j < je) {
     const uint64_t jg = j0 + (uint64_t)j;
-    if (j < je && (le(r, avg) || i == ie)) {
-      const uint32_t h = Ix[ppos(nl + j)];
-      const bool next = jg + 1 < H;
-      prob[h] = clamp01(quot(r, avg));
-      alias[h] = next ? Ix[ppos(nl + j + 1)] : h;
-      if (next) r = add_d(r - avg, Wv[ppos(nl + j + 1)]);
-      ++j;
+    const bool closing = (j < je) && (i == ie || le(r, avg));
+    double x;
+    if (closing) {
+      Ao[ppos(nl + j)] = (uint32_t)i;
+      x = (jg + 1 < H) ? Wv[ppos(nl + j + 1)] : 0.0;
     } else {
-      if (jg < H) {
-        Ao[ppos(i)] = Ix[ppos(nl + j)];
-        r = r - add_d(avg, -Wv[ppos(i)]);
-      } else {
-        Ao[ppos(i)] = Ix[ppos(i)];
-      }
-      ++i;
+      Ao[ppos(i)] = (jg < H) ? Ix[ppos(nl + j)] : Ix[ppos(i)];
+      x = Wv[ppos(i)];
     }
+    r = add_fast(r, add_d(navg, x));  // residual += incoming weight - W/N
+    i += closing ? 0 : 1;
+    j += closing ? 1 : 0;
   }
   wave_lds_sync();
 
-  // 5. light aliases, written in light (near item) order
-  for (int e = lane; e < nl; e += 64) alias[Ix[ppos(e)]] = Ao[ppos(e)];
+  // 5. heavy rows: residual at closing from the prefix sums
+  for (int e = lane; e < nh; e += 64) {
+    const int ic = (int)Ao[ppos(nl + e)];
+    const dd rc = (pack_sigma(Wv, 0, QL, S, ic) + pack_sigma(Wv, nl, QH, S, e + 1) + B) -
+                  mul_d(avg, (double)(ic + e));
+    const uint32_t h = Ix[ppos(nl + e)];
+    put_row<kRows>(out, h, clamp01(quot_fast(rc, dv)),
+                   (j0 + (uint64_t)e + 1 < H) ? Ix[ppos(nl + e + 1)] : h);
+  }
+
+  // 6. light rows, in light (near item) order: own share w/avg and alias
+  for (int e = lane; e < nl; e += 64)
+    put_row<kRows>(out, Ix[ppos(e)], clamp01(quot_fast(dd_make(Wv[ppos(e)], 0.0), dv)),
+                   Ao[ppos(e)]);
 }
 
 // Largest dynamic LDS allocation one block may make on the current device
@@ -721,14 +824,17 @@ static size_t device_max_lds_per_block() {
   return cache[dev];
 }
 
-int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias, void *d_ws,
-                 int32_t *d_status, const Layout &Lo, const SplitModel *model, uint64_t model_bytes,
-                 hipStream_t st) {
+int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alias,
+                 TableRow *d_rows, void *d_ws, int32_t *d_status, const Layout &Lo,
+                 const SplitModel *model, uint64_t model_bytes, hipStream_t st) {
   char *ws = (char *)d_ws;
   alias_ws_header *hdr = (alias_ws_header *)(ws + Lo.pub.header);
   ReducePart *parts = (ReducePart *)(ws + Lo.parts);
   TileSum *tsum = (TileSum *)(ws + Lo.tilesum);
   TilePrefix *tpre = (TilePrefix *)(ws + Lo.tilepre);
+  TileSum *gsum = (TileSum *)(ws + Lo.grpsum);
+  TilePrefix *gpre = (TilePrefix *)(ws + Lo.grppre);
+  const uint32_t groups = (Lo.pub.tiles + kScanGroup - 1) / kScanGroup;
   uint32_t *l_idx = (uint32_t *)(ws + Lo.pub.l_idx);
   uint32_t *h_idx = (uint32_t *)(ws + Lo.pub.h_idx);
   double *l_w = (double *)(ws + Lo.pub.l_w);
@@ -743,11 +849,13 @@ int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alia
   hipLaunchKernelGGL(k_reduce, dim3(rb), dim3(kReduceThreads), 0, st, d_w, n, parts);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, parts, rb, n, hdr, agg_l, agg_h,
                      d_status);
-  hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tsum, d_prob);
-  hipLaunchKernelGGL(k_tilescan, dim3(1), dim3(kScanThreads), 0, st, tsum, tiles, n, hdr, tpre,
+  hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tsum);
+  hipLaunchKernelGGL(k_tilescan, dim3(groups), dim3(kScanGroup), 0, st, tsum, tiles, hdr, tpre,
+                     gsum);
+  hipLaunchKernelGGL(k_groupscan, dim3(1), dim3(kScanGroup), 0, st, gsum, groups, n, hdr, gpre,
                      agg_l, agg_h);
-  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tpre, l_idx,
-                     l_w, h_idx, h_w, agg_l, agg_h);
+  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, d_w, n, hdr, tpre, gpre,
+                     l_idx, l_w, h_idx, h_w, agg_l, agg_h);
   hipLaunchKernelGGL(k_split, dim3((s + 1 + 255) / 256), dim3(256), 0, st, hdr, agg_l, agg_h, l_w,
                      h_w, s, Lo.chunk, n, sp_i, sp_j, spill, model, model_bytes,
                      &hdr->split_fallbacks);
@@ -757,9 +865,18 @@ int launch_build(const double *d_w, uint64_t n, double *d_prob, uint32_t *d_alia
   size_t waves = max_lds / per_wave;
   if (waves > (size_t)kPackWaves) waves = kPackWaves;
   if (waves == 0) return ALIAS_EINVAL;
-  hipLaunchKernelGGL(k_pack, dim3((s + waves - 1) / waves), dim3(64 * waves), waves * per_wave, st,
-                     hdr, l_idx, l_w, h_idx, h_w, sp_i, sp_j, spill, s, Lo.chunk, d_prob, d_alias,
-                     d_status);
+  TableOut out;
+  out.prob = d_prob;
+  out.alias = d_alias;
+  out.rows = d_rows;
+  if (d_rows)
+    hipLaunchKernelGGL(k_pack<true>, dim3((s + waves - 1) / waves), dim3(64 * waves),
+                       waves * per_wave, st, hdr, l_idx, l_w, h_idx, h_w, sp_i, sp_j, spill, s,
+                       Lo.chunk, out, d_status);
+  else
+    hipLaunchKernelGGL(k_pack<false>, dim3((s + waves - 1) / waves), dim3(64 * waves),
+                       waves * per_wave, st, hdr, l_idx, l_w, h_idx, h_w, sp_i, sp_j, spill, s,
+                       Lo.chunk, out, d_status);
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 

@@ -18,6 +18,15 @@ constexpr uint32_t kDefaultChunk = 1024;
 constexpr uint32_t kMinChunk = 64;
 constexpr uint32_t kMaxChunk = 2048;
 constexpr int kPackWaves = 4;            // sections per pack block (one wave each)
+constexpr int kScanGroup = 1024;         // tiles per block of the tile scan
+
+// One table row in the packed layout: 16 bytes, loaded and stored with a
+// single 128-bit access.
+struct __attribute__((aligned(16))) TableRow {
+  double prob;
+  uint32_t alias;
+  uint32_t pad;
+};
 
 // Per-tile light count and light / heavy weight sums (4096-item tiles).
 struct TileSum {
@@ -44,7 +53,9 @@ struct Layout {
   alias_ws_layout pub;
   uint64_t parts;      // ReducePart[reduce_blocks]
   uint64_t tilesum;    // TileSum per tile
-  uint64_t tilepre;    // TilePrefix per tile
+  uint64_t tilepre;    // TilePrefix per tile, within its group of 1024 tiles
+  uint64_t grpsum;     // TileSum per group of 1024 tiles
+  uint64_t grppre;     // TilePrefix per group
   uint32_t chunk;
 };
 
@@ -75,8 +86,11 @@ inline bool compute_layout(uint64_t n, const alias_build_opts *o, Layout *L) {
   };
   L->pub.header = take(sizeof(alias_ws_header));
   L->parts = take(rb * sizeof(ReducePart));
+  const uint64_t groups = (tiles + kScanGroup - 1) / kScanGroup;
   L->tilesum = take(tiles * sizeof(TileSum));
   L->tilepre = take(tiles * sizeof(TilePrefix));
+  L->grpsum = take(groups * sizeof(TileSum));
+  L->grppre = take(groups * sizeof(TilePrefix));
   L->pub.l_idx = take(n * 4);
   L->pub.h_idx = take(n * 4);
   L->pub.l_w = take(n * 8);

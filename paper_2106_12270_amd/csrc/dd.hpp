@@ -93,6 +93,41 @@ __device__ __forceinline__ double quot(dd a, dd b) {
   return q1 + q2;
 }
 
+// Divisor prepared once for many quotients: its dd value and the reciprocal
+// of its high part.
+struct Divisor {
+  double hi, lo, inv;
+};
+
+__device__ __forceinline__ Divisor make_divisor(dd b) {
+  Divisor d;
+  d.hi = b.hi;
+  d.lo = b.lo;
+  d.inv = 1.0 / b.hi;
+  return d;
+}
+
+// a / b rounded to one binary64 with one IEEE division: q1 = a.hi / b.hi,
+// exact remainder of that division (the remainder of a correctly rounded
+// quotient is representable), corrected by a.lo and b.lo, times 1/b.hi.
+// Equals quot() whenever a and b are plain doubles whose quotient is not a
+// rounding midpoint, and differs from it by at most one unit in the last
+// place otherwise.
+__device__ __forceinline__ double quot_fast(dd a, const Divisor &b) {
+  const double q1 = a.hi / b.hi;
+  const dd p = two_prod(b.hi, q1);
+  const double e = (((a.hi - p.hi) - p.lo) + a.lo) - b.lo * q1;
+  return q1 + e * b.inv;
+}
+
+// Addition without the renormalisation of the low parts (QD's sloppy add):
+// error bounded by a few units of 2^-104 times |a| + |b|, exact whenever the
+// operands and the sum fit in the two components.
+__device__ __forceinline__ dd add_fast(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  return quick_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+
 __device__ __forceinline__ double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
 
 // ---------------------------------------------------------------------------

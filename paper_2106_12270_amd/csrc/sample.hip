@@ -63,14 +63,56 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(const double *__restr
   }
 }
 
-int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
-                  uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st) {
-  if (count == 0) return ALIAS_OK;
+// The same draws from a table of 16-byte rows: one 128-bit gather per draw
+// instead of one for prob and another for alias.
+__global__ __launch_bounds__(kSampleThreads) void k_sample_rows(const TableRow *__restrict__ rows,
+                                                                uint64_t n, uint64_t count,
+                                                                uint32_t k0, uint32_t k1,
+                                                                uint64_t first, uint32_t table,
+                                                                uint32_t *__restrict__ out) {
+  const uint64_t G = (uint64_t)gridDim.x * kSampleThreads;
+  uint64_t q = (uint64_t)blockIdx.x * kSampleThreads + threadIdx.x;
+  for (; q + (kSampleUnroll - 1) * G < count; q += kSampleUnroll * G) {
+    uint64_t row[kSampleUnroll];
+    double coin[kSampleUnroll];
+    TableRow t[kSampleUnroll];
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u) draw_setup(first + q + u * G, table, k0, k1, n, row[u], coin[u]);
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u) t[u] = rows[row[u]];
+#pragma unroll
+    for (int u = 0; u < kSampleUnroll; ++u)
+      out[q + u * G] = (coin[u] < t[u].prob) ? (uint32_t)row[u] : t[u].alias;
+  }
+  for (; q < count; q += G) {
+    uint64_t row;
+    double coin;
+    draw_setup(first + q, table, k0, k1, n, row, coin);
+    const TableRow t = rows[row];
+    out[q] = (coin < t.prob) ? (uint32_t)row : t.alias;
+  }
+}
+
+static uint32_t sample_blocks(uint64_t count) {
   uint64_t blocks = (count + kSampleThreads * 8 - 1) / (kSampleThreads * 8);
   if (blocks > 16384) blocks = 16384;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(kSampleThreads), 0, st, prob, alias, n,
-                     count, (uint32_t)seed, (uint32_t)(seed >> 32), first, table, out);
+  return (uint32_t)blocks;
+}
+
+int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
+                  uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st) {
+  if (count == 0) return ALIAS_OK;
+  hipLaunchKernelGGL(k_sample, dim3(sample_blocks(count)), dim3(kSampleThreads), 0, st, prob, alias,
+                     n, count, (uint32_t)seed, (uint32_t)(seed >> 32), first, table, out);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+int launch_sample_rows(const TableRow *rows, uint64_t n, uint64_t count, uint64_t seed,
+                       uint64_t first, uint32_t table, uint32_t *out, hipStream_t st) {
+  if (count == 0) return ALIAS_OK;
+  hipLaunchKernelGGL(k_sample_rows, dim3(sample_blocks(count)), dim3(kSampleThreads), 0, st, rows,
+                     n, count, (uint32_t)seed, (uint32_t)(seed >> 32), first, table, out);
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 

@@ -101,6 +101,24 @@ def test_build_rejects_bad_arguments_before_launching():
     assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o5), None) == pkg.ALIAS_EMODEL
 
 
+def test_row_entry_points_reject_bad_arguments_before_launching():
+    L = pkg.lib()
+    n = 1000
+    wsb = pkg.workspace_bytes(n)
+    o = pkg.BuildOpts()
+    fake = C.c_void_p(0x10000)
+    assert L.alias_build_rows(fake, n, None, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert L.alias_build_rows(fake, n, C.c_void_p(0x10008), fake, wsb, fake, C.byref(o),
+                              None) == pkg.ALIAS_EINVAL
+    assert L.alias_build_rows(fake, n, fake, fake, wsb - 1, fake, C.byref(o),
+                              None) == pkg.ALIAS_EWORKSPACE
+    assert L.alias_build_rows(fake, 0, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample_rows(None, 10, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample_rows(C.c_void_p(0x10008), 10, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample_rows(fake, 0, 10, 1, 0, 0, fake, None) == pkg.ALIAS_EINVAL
+    assert L.alias_sample_rows(fake, 10, 0, 1, 0, 0, fake, None) == pkg.ALIAS_OK
+
+
 def test_sample_rejects_bad_arguments_before_launching():
     L = pkg.lib()
     fake = C.c_void_p(0x10000)

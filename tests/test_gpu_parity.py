@@ -133,6 +133,30 @@ def test_general_inputs(name, n):
     assert r["zero_violations"] == 0
 
 
+@pytest.mark.parametrize("name", ["powerlaw", "lognormal", "uniform"])
+@pytest.mark.parametrize("n", [(1 << 18) + 77, 4097, 1])
+def test_row_layout_equals_two_array_layout(name, n):
+    w = GENERAL[name](n) if n > 1 else np.array([2.5])
+    say("rows", name, n)
+    b, st, p, a = gpu_build(w, 1024)
+    rows = b.build_rows(torch.from_numpy(w).to(DEV))
+    torch.cuda.synchronize()
+    assert int(b.status.item()) == 0
+    r = rows.cpu().numpy()
+    assert np.array_equal(r[:, :2].copy().view(np.float64).ravel(), p)
+    assert np.array_equal(r[:, 2].view(np.uint32), a)
+    assert np.all(r[:, 3] == 0)
+    # same draws from both layouts, and equal to the oracle's
+    pd = torch.from_numpy(p).to(DEV)
+    ad = torch.from_numpy(a.view(np.int32)).to(DEV)
+    o1 = pkg.sample(pd, ad, 300_001, 77, first_draw=12345)
+    o2 = pkg.sample_rows(rows, 300_001, 77, first_draw=12345)
+    torch.cuda.synchronize()
+    ref = oracle.sample(p, a, 300_001, 77, first=12345)
+    assert np.array_equal(o1.cpu().numpy().view(np.uint32), ref)
+    assert np.array_equal(o2.cpu().numpy().view(np.uint32), ref)
+
+
 def test_build_is_deterministic():
     n = (1 << 20) + 3
     w = inputs.lognormal(n, 2.0, 3)
