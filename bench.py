@@ -38,11 +38,43 @@ def parse():
     ap.add_argument("--layout", choices=["rows", "soa"], default="rows",
                     help="table as 16-byte rows (one gather per draw) or two arrays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-n", type=int, default=None,
                     help="items in the CPU oracle's build sample (default: the workload's n)")
     ap.add_argument("--cpu-draws", type=int, default=50_000_000,
                     help="draws in the CPU oracle's sampling sample")
     return ap.parse_args()
+
+
+def csrc_hash():
+    """Hash of the HIP sources, recorded with rocprofv3 traffic summaries."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2106_12270_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, layout, kernel, launches_per_unit=1.0):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary,
+    or None when the summary is missing or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_{layout}.txt")
+    if not os.path.exists(path):
+        return None
+    sha = None
+    for line in open(path):
+        if line.startswith("# csrc_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif not line.startswith("#") and line.split() and line.split()[0].endswith(kernel):
+            if sha != csrc_hash():
+                return None
+            parts = line.split()
+            return (float(parts[-4]) + float(parts[-3])) * 1e9
+    return None
 
 
 def cpu_baseline(name, cpu_n, draws_sample):
@@ -96,6 +128,15 @@ def main():
 
     import paper_2106_12270_amd as pkg
     from paper_2106_12270_amd import inputs
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 8}))
+        return
 
     cfg = inputs.WORKLOADS[args.workload]
     n = cfg["n"]
@@ -167,6 +208,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(sample_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(sample_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_sample_rows" if rows_layout else "k_sample",
+                "traffic_source": "profiles/hbm_traffic_<workload>_<layout>.txt (rocprofv3 "
+                                  "FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
                 "bytes_per_launch": round(sample_bytes),
                 "bytes_model": ("per draw: 4 B out + one 16 B row" if rows_layout else
                                 "per draw: 4 B out + 8 B prob + 4 B alias x P(alias)"),
@@ -178,6 +221,11 @@ def main():
                 "bytes_per_launch": n * BUILD_BYTES_PER_ITEM,
                 "bytes_model": "52 B per item"}
 
+    kname = roof["kernel"].split(" ")[0]
+    tb = measured_traffic(args.workload, args.layout, kname)
+    if tb is not None and draws == cfg["draws"]:
+        roof["traffic"] = round(tb / 1e9, 3)
+        roof["traffic_unit"] = "GB per launch"
     result = {
         "metric": "alias build items/s (%HBM peak) + samples/s; learned vs binary split, 1 GPU",
         "value": n / (b_ms * 1e-3),
