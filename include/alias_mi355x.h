@@ -165,6 +165,62 @@ int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint
 int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
                       uint64_t first_draw, uint32_t table_id, uint32_t *d_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned split predictor (an added system pattern; the paper's splits use
+ * binary search, Sec. 4.1).  A small model maps a section boundary x = m/n
+ * to y = j/H, the fraction of heavy items closed after m rows; the split
+ * kernel checks a bracket of +-eps around the prediction and searches only
+ * inside it, falling back to the full binary search when the bracket check
+ * fails, so splits are exact whatever the model predicts.
+ * Model blob (device, 4-byte aligned): uint32 kind, uint32 segments,
+ * int32 eps (bracket half-width in units of 64 heavy entries), uint32
+ * nparams, then nparams float32 parameters:
+ *   ALIAS_MODEL_PWL  piecewise linear, `segments` equal segments on [0,1],
+ *                    segments+1 knot values;
+ *   ALIAS_MODEL_MLP  1 -> 32 -> 32 -> 1 with tanh hidden units, 1153 values:
+ *                    W1[32], b1[32], W2[32][32] (row = output), b2[32],
+ *                    W3[32], b3.
+ * ------------------------------------------------------------------------ */
+enum { ALIAS_MODEL_PWL = 1, ALIAS_MODEL_MLP = 2 };
+
+/* Bytes of a model blob (0 for an invalid kind or segment count; PWL allows
+ * 1..65536 segments). */
+size_t alias_split_model_bytes(uint32_t kind, uint32_t segments);
+
+/* Bytes of the training workspace for `points` training boundaries. */
+size_t alias_split_model_train_workspace_bytes(uint32_t kind, uint32_t segments, uint64_t points);
+
+/* Train a model on the GPU from the exact splits of a finished build: the
+ * training boundaries are the build's s+1 section boundaries, inputs
+ * x = m/n and targets j/H.  Loss: mean squared error; `epochs` full-batch
+ * Adam steps with step size `lr` decayed by a cosine schedule; gradients
+ * accumulated in fp64 in a fixed order, so the fit is bit-reproducible.
+ * Then eps = 1 + the largest error over the training boundaries.
+ *   d_build_ws, n, build_opts  workspace and options of the finished build
+ *   d_model      device blob of >= alias_split_model_bytes() bytes (written)
+ *   d_train_ws   device scratch of alias_split_model_train_workspace_bytes(
+ *                kind, segments, s+1) bytes, 256-byte aligned
+ *   d_loss       device double receiving the final loss, or NULL
+ * Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE or ALIAS_EHIP. */
+int alias_split_model_fit(const void *d_build_ws, uint64_t n, const alias_build_opts *build_opts,
+                          uint32_t kind, uint32_t segments, uint32_t epochs, float lr,
+                          void *d_model, size_t model_bytes, void *d_train_ws,
+                          size_t train_ws_bytes, double *d_loss, void *stream);
+
+/* Loss and gradient of a model's parameters over `points` pairs (x, t)
+ * (device float arrays; for ALIAS_MODEL_PWL x must be ascending).  d_grad:
+ * device double[nparams]; d_loss: device double.  The training kernels. */
+int alias_split_model_grad(uint32_t kind, uint32_t segments, const void *d_model,
+                           size_t model_bytes, const float *d_x, const float *d_t, uint64_t points,
+                           double *d_grad, double *d_loss, void *d_train_ws,
+                           size_t train_ws_bytes, void *stream);
+
+/* Recompute the splits of a finished build in d_ws with the split method in
+ * opts (binary, or learned with a model); the partition and prefix sums are
+ * reused and the table is not rewritten.  The number of sections whose
+ * bracket check failed is left in the workspace header (split_fallbacks). */
+int alias_resplit(void *d_ws, uint64_t n, const alias_build_opts *opts, void *stream);
+
 /* Human-readable text of a status code (static string). */
 const char *alias_status_str(int code);
 

@@ -61,6 +61,12 @@ def lib():
         L.oracle_mass.restype = C.c_int
         L.oracle_check.argtypes = [_ptr, _u64, _ptr, _ptr, _ptr, _ptr]
         L.oracle_check.restype = C.c_int
+        L.oracle_pwl_loss_grad.argtypes = [_ptr, _u32, _ptr, _ptr, _u64, _ptr]
+        L.oracle_pwl_loss_grad.restype = C.c_double
+        L.oracle_mlp_loss_grad.argtypes = [_ptr, _ptr, _ptr, _u64, _ptr]
+        L.oracle_mlp_loss_grad.restype = C.c_double
+        L.oracle_mlp_forward.argtypes = [_ptr, C.c_double]
+        L.oracle_mlp_forward.restype = C.c_double
         _lib = L
     return _lib
 
@@ -234,3 +240,31 @@ def chi2_gof(counts, expected, min_expected=5.0):
     stat = float(((gc - ge) ** 2 / ge).sum())
     dof = max(len(ge) - 1, 1)
     return stat, dof, float(_chi2.sf(stat, dof))
+
+
+MLP_PARAMS = 64 + 1024 + 64 + 1
+
+
+def pwl_loss_grad(p, x, t):
+    """fp64 loss and gradient of a K-segment piecewise-linear model."""
+    p = _f64(p)
+    x = _f64(x)
+    t = _f64(t)
+    g = np.empty_like(p)
+    loss = lib().oracle_pwl_loss_grad(_p(p), p.size - 1, _p(x), _p(t), x.size, _p(g))
+    return loss, g
+
+
+def mlp_loss_grad(theta, x, t):
+    """fp64 loss and gradient of the 1-32-32-1 tanh MLP."""
+    th = _f64(theta)
+    x = _f64(x)
+    t = _f64(t)
+    g = np.empty_like(th)
+    loss = lib().oracle_mlp_loss_grad(_p(th), _p(x), _p(t), x.size, _p(g))
+    return loss, g
+
+
+def mlp_forward(theta, x):
+    th = _f64(theta)
+    return np.array([lib().oracle_mlp_forward(_p(th), float(v)) for v in np.ravel(x)])

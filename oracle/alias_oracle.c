@@ -608,3 +608,92 @@ int oracle_check(const double *w, uint64_t n, const double *prob, const uint32_t
   free(ml);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned split models (an added system pattern, not in the paper): plain */
+/* fp64 losses and gradients, the reference for the GPU training kernels.   */
+/* A model maps x = m/n to y = j/H; loss = mean over points of (y - t)^2.   */
+/* Pinned by central finite differences in a CPU test.                      */
+/* ------------------------------------------------------------------------ */
+
+/* Piecewise linear with K segments on [0,1] (knots at k/K, K+1 values p):  */
+/* segment s = min(floor(x*K), K-1), f = x*K - s, y = p[s] + f*(p[s+1]-p[s]). */
+double oracle_pwl_loss_grad(const double *p, uint32_t K, const double *x, const double *t,
+                            uint64_t npts, double *grad) {
+  for (uint32_t k = 0; k <= K; ++k) grad[k] = 0.0;
+  double loss = 0.0;
+  for (uint64_t i = 0; i < npts; ++i) {
+    double u = x[i] * (double)K;
+    int64_t s = (int64_t)floor(u);
+    if (s < 0) s = 0;
+    if (s > (int64_t)K - 1) s = (int64_t)K - 1;
+    double f = u - (double)s;
+    double y = p[s] + f * (p[s + 1] - p[s]);
+    double r = y - t[i];
+    loss += r * r;
+    grad[s] += 2.0 * r * (1.0 - f);
+    grad[s + 1] += 2.0 * r * f;
+  }
+  for (uint32_t k = 0; k <= K; ++k) grad[k] /= (double)npts;
+  return loss / (double)npts;
+}
+
+/* MLP 1 -> 32 -> 32 -> 1 with tanh hidden units.  Parameter layout:        */
+/* W1[32], b1[32], W2[32][32] (row = output unit), b2[32], W3[32], b3.      */
+#define MLP_H 32
+double oracle_mlp_forward(const double *th, double x) {
+  const double *W1 = th, *b1 = th + 32, *W2 = th + 64, *b2 = th + 64 + 1024, *W3 = th + 64 + 1024 + 32;
+  double b3 = th[64 + 1024 + 64];
+  double h1[MLP_H];
+  for (int a = 0; a < MLP_H; ++a) h1[a] = tanh(W1[a] * x + b1[a]);
+  double y = b3;
+  for (int b = 0; b < MLP_H; ++b) {
+    double z = b2[b];
+    for (int a = 0; a < MLP_H; ++a) z += W2[b * MLP_H + a] * h1[a];
+    y += W3[b] * tanh(z);
+  }
+  return y;
+}
+
+double oracle_mlp_loss_grad(const double *th, const double *x, const double *t, uint64_t npts,
+                            double *grad) {
+  const int NP = 64 + 1024 + 64 + 1;
+  const double *W1 = th, *b1 = th + 32, *W2 = th + 64, *b2 = th + 64 + 1024, *W3 = th + 64 + 1024 + 32;
+  double b3 = th[64 + 1024 + 64];
+  double *gW1 = grad, *gb1 = grad + 32, *gW2 = grad + 64, *gb2 = grad + 64 + 1024,
+         *gW3 = grad + 64 + 1024 + 32, *gb3 = grad + 64 + 1024 + 64;
+  for (int k = 0; k < NP; ++k) grad[k] = 0.0;
+  double loss = 0.0;
+  for (uint64_t i = 0; i < npts; ++i) {
+    double h1[MLP_H], h2[MLP_H], dz2[MLP_H];
+    for (int a = 0; a < MLP_H; ++a) h1[a] = tanh(W1[a] * x[i] + b1[a]);
+    double y = b3;
+    for (int b = 0; b < MLP_H; ++b) {
+      double z = b2[b];
+      for (int a = 0; a < MLP_H; ++a) z += W2[b * MLP_H + a] * h1[a];
+      h2[b] = tanh(z);
+      y += W3[b] * h2[b];
+    }
+    double r = y - t[i];
+    loss += r * r;
+    double dy = 2.0 * r;
+    *gb3 += dy;
+    for (int b = 0; b < MLP_H; ++b) {
+      gW3[b] += dy * h2[b];
+      dz2[b] = dy * W3[b] * (1.0 - h2[b] * h2[b]);
+      gb2[b] += dz2[b];
+    }
+    for (int a = 0; a < MLP_H; ++a) {
+      double dh1 = 0.0;
+      for (int b = 0; b < MLP_H; ++b) {
+        gW2[b * MLP_H + a] += dz2[b] * h1[a];
+        dh1 += W2[b * MLP_H + a] * dz2[b];
+      }
+      double dz1 = dh1 * (1.0 - h1[a] * h1[a]);
+      gW1[a] += dz1 * x[i];
+      gb1[a] += dz1;
+    }
+  }
+  for (int k = 0; k < NP; ++k) grad[k] /= (double)npts;
+  return loss / (double)npts;
+}

@@ -23,6 +23,8 @@ ALIAS_OK, ALIAS_EINVAL, ALIAS_EWEIGHTS, ALIAS_EWORKSPACE, ALIAS_EHIP, ALIAS_EMOD
     0, -1, -2, -3, -4, -5)
 ALIAS_EINTERNAL = -6
 SPLIT_BINARY, SPLIT_LEARNED = 0, 1
+MODEL_PWL, MODEL_MLP = 1, 2
+MODEL_KINDS = {"pwl": MODEL_PWL, "mlp": MODEL_MLP}
 
 
 class AliasError(RuntimeError):
@@ -83,6 +85,18 @@ def lib():
         L.alias_build_rows.restype = C.c_int
         L.alias_sample_rows.argtypes = [vp, u64, u64, u64, u64, u32, vp, vp]
         L.alias_sample_rows.restype = C.c_int
+        L.alias_split_model_bytes.argtypes = [u32, u32]
+        L.alias_split_model_bytes.restype = C.c_size_t
+        L.alias_split_model_train_workspace_bytes.argtypes = [u32, u32, u64]
+        L.alias_split_model_train_workspace_bytes.restype = C.c_size_t
+        L.alias_split_model_fit.argtypes = [vp, u64, C.POINTER(BuildOpts), u32, u32, u32,
+                                            C.c_float, vp, C.c_size_t, vp, C.c_size_t, vp, vp]
+        L.alias_split_model_fit.restype = C.c_int
+        L.alias_split_model_grad.argtypes = [u32, u32, vp, C.c_size_t, vp, vp, u64, vp, vp, vp,
+                                             C.c_size_t, vp]
+        L.alias_split_model_grad.restype = C.c_int
+        L.alias_resplit.argtypes = [vp, u64, C.POINTER(BuildOpts), vp]
+        L.alias_resplit.restype = C.c_int
         L.alias_status_str.argtypes = [C.c_int]
         L.alias_status_str.restype = C.c_char_p
         L.alias_version.argtypes = []
@@ -205,6 +219,41 @@ class Builder:
             raise AliasError(st, "alias_build_rows")
         return rows
 
+    def fit_split_model(self, kind="pwl", segments=4096, epochs=400, lr=0.02, stream=None):
+        """Train a split model on the splits of the last build (on the GPU).
+        Returns (model blob as a uint8 tensor, final loss as a 1-element
+        float64 tensor)."""
+        import torch
+
+        k = MODEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+        mb = lib().alias_split_model_bytes(k, int(segments))
+        if mb == 0:
+            raise AliasError(ALIAS_EINVAL, "alias_split_model_bytes")
+        points = int(self.layout.sections) + 1
+        tb = lib().alias_split_model_train_workspace_bytes(k, int(segments), points)
+        model = torch.empty(mb, dtype=torch.uint8, device=self.ws.device)
+        tws = torch.empty(tb, dtype=torch.uint8, device=self.ws.device)
+        loss = torch.zeros(1, dtype=torch.float64, device=self.ws.device)
+        o = _opts(self.chunk, "binary")
+        st = lib().alias_split_model_fit(C.c_void_p(self.ws.data_ptr()), self.n, C.byref(o), k,
+                                         int(segments), int(epochs), float(lr),
+                                         C.c_void_p(model.data_ptr()), mb,
+                                         C.c_void_p(tws.data_ptr()), tb,
+                                         C.c_void_p(loss.data_ptr()), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_split_model_fit")
+        self._train_ws = tws
+        return model, loss
+
+    def resplit(self, model=None, stream=None):
+        """Recompute the splits of the last build: binary if model is None,
+        else learned with that model."""
+        o = _opts(self.chunk, "learned" if model is not None else "binary", model)
+        st = lib().alias_resplit(C.c_void_p(self.ws.data_ptr()), self.n, C.byref(o),
+                                 _stream(stream))
+        if st:
+            raise AliasError(st, "alias_resplit")
+
     # --- inspection of the last build (reads device memory; synchronises) ---
     def _view(self, off, count, dtype):
         import torch
@@ -296,6 +345,50 @@ def sample_rows(rows, count, seed, first_draw=0, table_id=0, out=None, stream=No
     if st:
         raise AliasError(st, "alias_sample_rows")
     return out
+
+
+def model_header(model):
+    """(kind, segments, eps, nparams) of a model blob (synchronises)."""
+    import numpy as np
+
+    h = model[:16].cpu().numpy().view(np.uint32)
+    return int(h[0]), int(h[1]), int(h[2].view(np.int32)), int(h[3])
+
+
+def model_grad(kind, segments, model, x, t, stream=None):
+    """Loss and gradient (float64) of a model over points (x, t) with the
+    device training kernels."""
+    import torch
+
+    k = MODEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _check_dev(x, torch.float32, "x")
+    _check_dev(t, torch.float32, "t")
+    npar = (int(segments) + 1) if k == MODEL_PWL else 1153
+    grad = torch.empty(npar, dtype=torch.float64, device=x.device)
+    loss = torch.empty(1, dtype=torch.float64, device=x.device)
+    tb = lib().alias_split_model_train_workspace_bytes(k, int(segments), x.numel())
+    tws = torch.empty(tb, dtype=torch.uint8, device=x.device)
+    st = lib().alias_split_model_grad(k, int(segments), C.c_void_p(model.data_ptr()),
+                                      model.numel(), C.c_void_p(x.data_ptr()),
+                                      C.c_void_p(t.data_ptr()), x.numel(),
+                                      C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                      C.c_void_p(tws.data_ptr()), tb, _stream(stream))
+    if st:
+        raise AliasError(st, "alias_split_model_grad")
+    return loss, grad
+
+
+def make_model(kind, params, segments=0, eps=0):
+    """A model blob (uint8 CUDA tensor) from explicit float32 parameters."""
+    import numpy as np
+    import torch
+
+    k = MODEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    hdr = np.array([k, segments if k == MODEL_PWL else 0, 0, params.size], dtype=np.uint32)
+    hdr[2] = np.array([eps], dtype=np.int32).view(np.uint32)[0]
+    blob = np.concatenate([hdr.view(np.uint8), params.view(np.uint8)])
+    return torch.from_numpy(blob).to("cuda")
 
 
 def sample(prob, alias, count, seed, first_draw=0, table_id=0, out=None, stream=None):

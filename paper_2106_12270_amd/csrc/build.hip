@@ -808,6 +808,27 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(
                    Ao[ppos(e)]);
 }
 
+__global__ void k_reset_fallbacks(alias_ws_header *hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->split_fallbacks = 0;
+}
+
+// Recompute the splits of a finished build (binary or learned); the pack is
+// not rerun.  Used to compare split methods on the same partition.
+int launch_split_only(void *d_ws, uint64_t n, const Layout &Lo, const SplitModel *model,
+                      uint64_t model_bytes, hipStream_t st) {
+  char *ws = (char *)d_ws;
+  alias_ws_header *hdr = (alias_ws_header *)(ws + Lo.pub.header);
+  const uint32_t s = Lo.pub.sections;
+  hipLaunchKernelGGL(k_reset_fallbacks, dim3(1), dim3(64), 0, st, hdr);
+  hipLaunchKernelGGL(k_split, dim3((s + 1 + 255) / 256), dim3(256), 0, st, hdr,
+                     (const dd *)(ws + Lo.pub.agg_l), (const dd *)(ws + Lo.pub.agg_h),
+                     (const double *)(ws + Lo.pub.l_w), (const double *)(ws + Lo.pub.h_w), s,
+                     Lo.chunk, n, (uint32_t *)(ws + Lo.pub.split_i),
+                     (uint32_t *)(ws + Lo.pub.split_j), (dd *)(ws + Lo.pub.spill), model,
+                     model_bytes, &hdr->split_fallbacks);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
 // Largest dynamic LDS allocation one block may make on the current device
 // (queried once per device; the attribute query does not synchronise).
 static size_t device_max_lds_per_block() {

@@ -1,0 +1,507 @@
+// Learned split predictor: training on the device.
+//
+// The model maps a section boundary x = m/n to y = j/H, the fraction of
+// heavy items closed after m rows.  Its training data are the exact splits
+// of a finished build (the method's own output).  Loss: mean over the
+// boundaries of (y - t)^2.  Parameters are FP32; gradients are accumulated in
+// FP64 in a fixed order (per-knot loops for the piecewise-linear model,
+// per-parameter loops over LDS batches for the MLP, fixed-order reduction of
+// block partials), so a fit is bit-reproducible.  Adam updates the
+// parameters.  Finally the largest prediction error over the training
+// boundaries, in units of 64 heavy entries, plus one, becomes the bracket
+// half-width that the split kernel checks before it trusts a prediction.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "alias_mi355x.h"
+#include "common.hpp"
+#include "learned.hpp"
+#include "philox.hpp"
+
+namespace amdalias {
+
+constexpr int kLearnThreads = 256;
+constexpr int kMlpBatch = 128;
+constexpr uint32_t kMaxPwlSegments = 1u << 16;
+
+struct TrainLayout {
+  uint64_t x, t, q, grad, m, v, part, loss_part, misc, total;
+  uint32_t points, nparams, blocks;
+};
+
+__host__ __device__ inline uint32_t model_nparams(uint32_t kind, uint32_t segments) {
+  return kind == kModelPWL ? segments + 1 : (uint32_t)kMlpParams;
+}
+
+inline bool train_layout(uint32_t kind, uint32_t segments, uint64_t points, TrainLayout *T) {
+  if (kind == kModelPWL) {
+    if (segments < 1 || segments > kMaxPwlSegments) return false;
+  } else if (kind != kModelMLP) {
+    return false;
+  }
+  if (points < 1 || points > (1ull << 31)) return false;
+  const uint32_t np = model_nparams(kind, segments);
+  uint32_t blocks = (uint32_t)((points + 4095) / 4096);
+  if (blocks > 256) blocks = 256;
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) {
+    uint64_t at = off;
+    off = align256(off + b);
+    return at;
+  };
+  T->x = take(points * 4);
+  T->t = take(points * 4);
+  T->q = take(points * 4);
+  T->grad = take((uint64_t)np * 8);
+  T->m = take((uint64_t)np * 4);
+  T->v = take((uint64_t)np * 4);
+  T->part = take((uint64_t)blocks * np * 8);
+  T->loss_part = take((uint64_t)blocks * 8);
+  T->misc = take(64);
+  T->total = off;
+  T->points = (uint32_t)points;
+  T->nparams = np;
+  T->blocks = blocks;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// training data from the splits of a finished build
+// ---------------------------------------------------------------------------
+__global__ void k_targets(const alias_ws_header *hdr, const uint32_t *__restrict__ split_j,
+                          uint32_t points, uint32_t chunk, uint64_t n, float *__restrict__ x,
+                          float *__restrict__ t, int32_t *__restrict__ q) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= points) return;
+  const uint64_t m = ((uint64_t)k * chunk < n) ? (uint64_t)k * chunk : n;
+  const uint64_t H = hdr->H;
+  const uint32_t j = split_j[k];
+  x[k] = (float)((double)m / (double)n);
+  t[k] = H ? (float)((double)j / (double)H) : 0.0f;
+  q[k] = (int32_t)(j / kAggStride);
+}
+
+// ---------------------------------------------------------------------------
+// model initialisation: PWL = identity, MLP = small deterministic values
+// ---------------------------------------------------------------------------
+__global__ void k_init_model(SplitModel *M, uint32_t kind, uint32_t segments, float *m, float *v) {
+  const uint32_t np = model_nparams(kind, segments);
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {
+    M->kind = kind;
+    M->segments = kind == kModelPWL ? segments : 0u;
+    M->eps_q = 0x3fffffff;  // no bracket until the fit is finished
+    M->nparams = np;
+  }
+  if (e >= np) return;
+  m[e] = 0.0f;
+  v[e] = 0.0f;
+  if (kind == kModelPWL) {
+    M->params[e] = (float)e / (float)segments;
+    return;
+  }
+  u32x4 c;
+  c.x = e;
+  c.y = 0x5EEDu;
+  c.z = 0u;
+  c.w = 0u;
+  const u32x4 r = philox4x32_10(c, 0x1234567u, 0x89ABCDEu);
+  const float u = ((float)(r.x >> 8) * (1.0f / 16777216.0f)) * 2.0f - 1.0f;  // [-1, 1)
+  float val;
+  if (e < 32)
+    val = 3.0f * u;  // W1: spread the first-layer slopes
+  else if (e < 64)
+    val = 1.5f * u;  // b1
+  else if (e < 64 + 1024)
+    val = u * 0.35f;  // W2
+  else if (e < 64 + 1024 + 32)
+    val = 0.1f * u;  // b2
+  else if (e < 64 + 1024 + 64)
+    val = 0.1f * u;  // W3
+  else
+    val = 0.5f;  // b3: the middle of the target range
+  M->params[e] = val;
+}
+
+// ---------------------------------------------------------------------------
+// loss: per-block partial sums of (y - t)^2 in fp64 (fixed order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float model_eval(const SplitModel *M, float x) {
+  return M->kind == kModelPWL ? pwl_forward(M->params, M->segments, x) : mlp_forward(M->params, x);
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double *s /*[kLearnThreads/64]*/) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) s[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += s[k];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kLearnThreads) void k_loss_partial(const SplitModel *M,
+                                                                const float *__restrict__ x,
+                                                                const float *__restrict__ t,
+                                                                uint32_t points,
+                                                                double *__restrict__ part) {
+  __shared__ double s[kLearnThreads / 64];
+  const uint32_t per = (points + gridDim.x - 1) / gridDim.x;
+  const uint32_t b = blockIdx.x * per, e = (b + per < points) ? b + per : points;
+  double acc = 0.0;
+  for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const double r = (double)model_eval(M, x[i]) - (double)t[i];
+    acc += r * r;
+  }
+  acc = block_sum_f64(acc, s);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// PWL gradient: one thread per knot over the points of its two segments
+// (points sorted by x, so each segment's points are a contiguous range)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pwl_seg(float x, uint32_t K) {
+  int s = (int)(x * (float)K);
+  if (s < 0) s = 0;
+  if (s > (int)K - 1) s = (int)K - 1;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t first_point_of_seg(const float *x, uint32_t points, uint32_t K,
+                                                       int seg) {
+  uint32_t lo = 0, hi = points;  // first i with pwl_seg(x[i]) >= seg
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (pwl_seg(x[mid], K) >= seg)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kLearnThreads) void k_pwl_grad(const SplitModel *M,
+                                                            const float *__restrict__ x,
+                                                            const float *__restrict__ t,
+                                                            uint32_t points,
+                                                            double *__restrict__ grad) {
+  const uint32_t K = M->segments;
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > K) return;
+  const float *p = M->params;
+  double acc = 0.0;
+  for (int seg = (int)s - 1; seg <= (int)s; ++seg) {
+    if (seg < 0 || seg >= (int)K) continue;
+    const uint32_t lo = first_point_of_seg(x, points, K, seg);
+    const uint32_t hi = first_point_of_seg(x, points, K, seg + 1);
+    for (uint32_t i = lo; i < hi; ++i) {
+      const float u = x[i] * (float)K;
+      const float f = u - (float)seg;
+      const float y = p[seg] + f * (p[seg + 1] - p[seg]);
+      const double r = (double)y - (double)t[i];
+      acc += 2.0 * r * (double)((seg == (int)s) ? (1.0f - f) : f);
+    }
+  }
+  grad[s] = acc / (double)points;
+}
+
+// ---------------------------------------------------------------------------
+// MLP gradient: blocks own contiguous point ranges; per batch of 128 points
+// each thread runs one point forward and backward into LDS, then each thread
+// accumulates the parameters it owns over the batch in fixed order.
+// ---------------------------------------------------------------------------
+struct MlpShared {
+  float h1[kMlpBatch][kMlpHidden + 1];
+  float h2[kMlpBatch][kMlpHidden + 1];
+  float dz1[kMlpBatch][kMlpHidden + 1];
+  float dz2[kMlpBatch][kMlpHidden + 1];
+  float x[kMlpBatch], dy[kMlpBatch];
+  double red[kLearnThreads / 64];
+};
+
+__global__ __launch_bounds__(kLearnThreads) void k_mlp_grad_partial(
+    const SplitModel *M, const float *__restrict__ x, const float *__restrict__ t, uint32_t points,
+    double *__restrict__ part, double *__restrict__ loss_part) {
+  __shared__ MlpShared S;
+  const float *P = M->params;
+  const float *W1 = P, *b1 = P + 32, *W2 = P + 64, *b2 = P + 64 + 1024, *W3 = P + 64 + 1024 + 32;
+  const float b3 = P[64 + 1024 + 64];
+  const uint32_t per = (points + gridDim.x - 1) / gridDim.x;
+  const uint32_t b0 = blockIdx.x * per, e0 = (b0 + per < points) ? b0 + per : points;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double lacc = 0.0;
+  for (uint32_t base = b0; base < e0; base += kMlpBatch) {
+    const uint32_t cnt = (e0 - base < (uint32_t)kMlpBatch) ? e0 - base : (uint32_t)kMlpBatch;
+    if (threadIdx.x < cnt) {
+      const int pi = threadIdx.x;
+      const float xi = x[base + pi];
+      float h1[kMlpHidden];
+#pragma unroll
+      for (int a = 0; a < kMlpHidden; ++a) {
+        h1[a] = tanhf(W1[a] * xi + b1[a]);
+        S.h1[pi][a] = h1[a];
+      }
+      float y = b3;
+      float h2[kMlpHidden];
+      for (int b = 0; b < kMlpHidden; ++b) {
+        float z = b2[b];
+#pragma unroll
+        for (int a = 0; a < kMlpHidden; ++a) z += W2[b * kMlpHidden + a] * h1[a];
+        h2[b] = tanhf(z);
+        S.h2[pi][b] = h2[b];
+        y += W3[b] * h2[b];
+      }
+      const float r = y - t[base + pi];
+      lacc += (double)r * (double)r;
+      const float dy = 2.0f * r;
+      S.dy[pi] = dy;
+      S.x[pi] = xi;
+      float dz2[kMlpHidden];
+#pragma unroll
+      for (int b = 0; b < kMlpHidden; ++b) {
+        dz2[b] = dy * W3[b] * (1.0f - h2[b] * h2[b]);
+        S.dz2[pi][b] = dz2[b];
+      }
+      for (int a = 0; a < kMlpHidden; ++a) {
+        float dh1 = 0.0f;
+#pragma unroll
+        for (int b = 0; b < kMlpHidden; ++b) dh1 += W2[b * kMlpHidden + a] * dz2[b];
+        S.dz1[pi][a] = dh1 * (1.0f - h1[a] * h1[a]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      const int e = threadIdx.x + r * kLearnThreads;
+      if (e >= kMlpParams) break;
+      double sacc = 0.0;
+      for (uint32_t pi = 0; pi < cnt; ++pi) {
+        float g;
+        if (e < 32)
+          g = S.dz1[pi][e] * S.x[pi];
+        else if (e < 64)
+          g = S.dz1[pi][e - 32];
+        else if (e < 64 + 1024)
+          g = S.dz2[pi][(e - 64) >> 5] * S.h1[pi][(e - 64) & 31];
+        else if (e < 64 + 1024 + 32)
+          g = S.dz2[pi][e - 64 - 1024];
+        else if (e < 64 + 1024 + 64)
+          g = S.dy[pi] * S.h2[pi][e - 64 - 1024 - 32];
+        else
+          g = S.dy[pi];
+        sacc += (double)g;
+      }
+      acc[r] += sacc;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const int e = threadIdx.x + r * kLearnThreads;
+    if (e < kMlpParams) part[(uint64_t)blockIdx.x * kMlpParams + e] = acc[r];
+  }
+  lacc = block_sum_f64(lacc, S.red);
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = lacc;
+}
+
+// grad[e] = sum over blocks (in block order) of part[b][e] / points
+__global__ void k_reduce_parts(const double *__restrict__ part, uint32_t blocks, uint32_t np,
+                               uint32_t points, double *__restrict__ grad) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np) return;
+  double s = 0.0;
+  for (uint32_t b = 0; b < blocks; ++b) s += part[(uint64_t)b * np + e];
+  grad[e] = s / (double)points;
+}
+
+__global__ void k_loss_final(const double *__restrict__ loss_part, uint32_t blocks, uint32_t points,
+                             double *loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (uint32_t b = 0; b < blocks; ++b) s += loss_part[b];
+  *loss = s / (double)points;
+}
+
+// ---------------------------------------------------------------------------
+// Adam (Kingma & Ba) with bias correction factors computed on the host
+// ---------------------------------------------------------------------------
+__global__ void k_adam(SplitModel *M, const double *__restrict__ grad, float *__restrict__ mo,
+                       float *__restrict__ ve, uint32_t np, float lr, float bc1, float bc2) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np) return;
+  const float g = (float)grad[e];
+  const float m = 0.9f * mo[e] + 0.1f * g;
+  const float v = 0.999f * ve[e] + 0.001f * g * g;
+  mo[e] = m;
+  ve[e] = v;
+  M->params[e] -= lr * (m / bc1) / (sqrtf(v / bc2) + 1e-12f);
+}
+
+// ---------------------------------------------------------------------------
+// error bound: largest |predicted - true| aggregate index over the training
+// boundaries; the bracket half-width is that plus one
+// ---------------------------------------------------------------------------
+__global__ void k_model_err(const SplitModel *M, const alias_ws_header *hdr,
+                            const int32_t *__restrict__ q, uint32_t points, uint32_t chunk,
+                            uint64_t n, int32_t *maxerr) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t err = 0;
+  if (k < points) {
+    const uint64_t m = ((uint64_t)k * chunk < n) ? (uint64_t)k * chunk : n;
+    int64_t d = learned_predict_q(M, m, n, hdr->H) - (int64_t)q[k];
+    if (d < 0) d = -d;
+    err = d > 0x3ffffff ? 0x3ffffff : (int32_t)d;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int32_t o = __shfl_xor(err, m, 64);
+    err = o > err ? o : err;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(maxerr, err);
+}
+
+__global__ void k_zero_i32(int32_t *p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+__global__ void k_model_finish(SplitModel *M, const int32_t *maxerr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) M->eps_q = *maxerr + 1;
+}
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+static int launch_grad(uint32_t kind, const SplitModel *M, const float *x, const float *t,
+                       uint32_t points, const TrainLayout &T, char *tw, double *grad, double *loss,
+                       hipStream_t st) {
+  double *part = (double *)(tw + T.part), *lpart = (double *)(tw + T.loss_part);
+  const uint32_t np = T.nparams;
+  if (kind == kModelPWL) {
+    hipLaunchKernelGGL(k_pwl_grad, dim3((np + kLearnThreads - 1) / kLearnThreads),
+                       dim3(kLearnThreads), 0, st, M, x, t, points, grad);
+    if (loss) {
+      hipLaunchKernelGGL(k_loss_partial, dim3(T.blocks), dim3(kLearnThreads), 0, st, M, x, t,
+                         points, lpart);
+      hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, lpart, T.blocks, points, loss);
+    }
+  } else {
+    hipLaunchKernelGGL(k_mlp_grad_partial, dim3(T.blocks), dim3(kLearnThreads), 0, st, M, x, t,
+                       points, part, lpart);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((np + 255) / 256), dim3(256), 0, st, part, T.blocks,
+                       np, points, grad);
+    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, lpart, T.blocks, points, loss);
+  }
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+int launch_split_only(void *d_ws, uint64_t n, const Layout &Lo, const SplitModel *model,
+                      uint64_t model_bytes, hipStream_t st);
+
+}  // namespace amdalias
+
+using namespace amdalias;
+
+extern "C" {
+
+size_t alias_split_model_bytes(uint32_t kind, uint32_t segments) {
+  if (kind == ALIAS_MODEL_PWL && (segments < 1 || segments > kMaxPwlSegments)) return 0;
+  if (kind != ALIAS_MODEL_PWL && kind != ALIAS_MODEL_MLP) return 0;
+  return 16 + 4ull * model_nparams(kind, segments);
+}
+
+size_t alias_split_model_train_workspace_bytes(uint32_t kind, uint32_t segments, uint64_t points) {
+  TrainLayout T;
+  if (!train_layout(kind, segments, points, &T)) return 0;
+  return (size_t)T.total;
+}
+
+int alias_split_model_fit(const void *d_build_ws, uint64_t n, const alias_build_opts *build_opts,
+                          uint32_t kind, uint32_t segments, uint32_t epochs, float lr,
+                          void *d_model, size_t model_bytes, void *d_train_ws,
+                          size_t train_ws_bytes, double *d_loss, void *stream) {
+  Layout L;
+  TrainLayout T;
+  if (!d_build_ws || !d_model || !d_train_ws) return ALIAS_EINVAL;
+  if (((uintptr_t)d_build_ws & 255) || ((uintptr_t)d_model & 3) || ((uintptr_t)d_train_ws & 255))
+    return ALIAS_EINVAL;
+  if (!compute_layout(n, build_opts, &L)) return ALIAS_EINVAL;
+  const uint32_t points = L.pub.sections + 1;
+  if (!train_layout(kind, segments, points, &T)) return ALIAS_EINVAL;
+  if (model_bytes < alias_split_model_bytes(kind, segments)) return ALIAS_EINVAL;
+  if (train_ws_bytes < T.total) return ALIAS_EWORKSPACE;
+  if (!(lr > 0.0f) || epochs > 1000000) return ALIAS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const char *bw = (const char *)d_build_ws;
+  char *tw = (char *)d_train_ws;
+  const alias_ws_header *hdr = (const alias_ws_header *)(bw + L.pub.header);
+  const uint32_t *split_j = (const uint32_t *)(bw + L.pub.split_j);
+  float *x = (float *)(tw + T.x), *t = (float *)(tw + T.t);
+  int32_t *q = (int32_t *)(tw + T.q);
+  double *grad = (double *)(tw + T.grad);
+  float *mo = (float *)(tw + T.m), *ve = (float *)(tw + T.v);
+  int32_t *maxerr = (int32_t *)(tw + T.misc);
+  double *loss = d_loss ? d_loss : (double *)(tw + T.misc + 8);
+  SplitModel *M = (SplitModel *)d_model;
+  const uint32_t np = T.nparams;
+
+  hipLaunchKernelGGL(k_targets, dim3((points + 255) / 256), dim3(256), 0, st, hdr, split_j, points,
+                     L.chunk, n, x, t, q);
+  hipLaunchKernelGGL(k_init_model, dim3((np + 255) / 256), dim3(256), 0, st, M, kind, segments, mo,
+                     ve);
+  // Adam with a cosine-decayed step size
+  const double b1 = 0.9, b2 = 0.999;
+  double p1 = 1.0, p2 = 1.0;
+  for (uint32_t e = 0; e < epochs; ++e) {
+    const bool last = (e + 1 == epochs);
+    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, last ? loss : nullptr, st);
+    if (rc) return rc;
+    p1 *= b1;
+    p2 *= b2;
+    const double cosf_ = 0.5 * (1.0 + cos(3.141592653589793 * (double)e / (double)epochs));
+    const float lre = (float)(lr * (0.02 + 0.98 * cosf_));
+    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, M, grad, mo, ve, np, lre,
+                       (float)(1.0 - p1), (float)(1.0 - p2));
+  }
+  if (epochs == 0) {
+    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, loss, st);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, maxerr);
+  hipLaunchKernelGGL(k_model_err, dim3((points + 255) / 256), dim3(256), 0, st, M, hdr, q, points,
+                     L.chunk, n, maxerr);
+  hipLaunchKernelGGL(k_model_finish, dim3(1), dim3(64), 0, st, M, maxerr);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+int alias_split_model_grad(uint32_t kind, uint32_t segments, const void *d_model,
+                           size_t model_bytes, const float *d_x, const float *d_t, uint64_t points,
+                           double *d_grad, double *d_loss, void *d_train_ws,
+                           size_t train_ws_bytes, void *stream) {
+  TrainLayout T;
+  if (!d_model || !d_x || !d_t || !d_grad || !d_loss || !d_train_ws) return ALIAS_EINVAL;
+  if (!train_layout(kind, segments, points, &T)) return ALIAS_EINVAL;
+  if (model_bytes < alias_split_model_bytes(kind, segments)) return ALIAS_EINVAL;
+  if (train_ws_bytes < T.total || ((uintptr_t)d_train_ws & 255)) return ALIAS_EWORKSPACE;
+  return launch_grad(kind, (const SplitModel *)d_model, d_x, d_t, (uint32_t)points, T,
+                     (char *)d_train_ws, d_grad, d_loss, (hipStream_t)stream);
+}
+
+int alias_resplit(void *d_ws, uint64_t n, const alias_build_opts *opts, void *stream) {
+  Layout L;
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return ALIAS_EINVAL;
+  if (!compute_layout(n, opts, &L)) return ALIAS_EINVAL;
+  const SplitModel *model = nullptr;
+  uint64_t model_bytes = 0;
+  if (opts && opts->split_method == ALIAS_SPLIT_LEARNED) {
+    if (!opts->split_model || opts->split_model_bytes < 16 || ((uintptr_t)opts->split_model & 3))
+      return ALIAS_EMODEL;
+    model = (const SplitModel *)opts->split_model;
+    model_bytes = opts->split_model_bytes;
+  }
+  return launch_split_only(d_ws, n, L, model, model_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+"""GPU tests of the learned split predictor (an added system pattern).
+
+- The device training kernels' gradients equal the fp64 CPU references
+  (which are pinned by finite differences in test_learned_cpu.py).
+- A model trained on a build's own splits yields splits identical to the
+  binary search, with no fallback, and the learned build's table is the
+  binary build's table bit for bit.
+- Malformed or untrained models only cost fallbacks; splits stay exact.
+- The trained model shrinks the search: fewer dependent probes per split.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_2106_12270_amd as pkg
+from paper_2106_12270_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.lib()
+    oracle.lib()
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("K", [1, 64, 4096])
+def test_pwl_gradient_matches_cpu(K):
+    rng = np.random.default_rng(K)
+    p = rng.random(K + 1).astype(np.float32)
+    x = np.sort(rng.random(20000)).astype(np.float32)
+    x[:3] = 0.0
+    x[-2:] = 1.0
+    t = (np.sqrt(x) + 0.05 * rng.standard_normal(x.size)).astype(np.float32)
+    say("pwl grad", K)
+    model = pkg.make_model("pwl", p, segments=K)
+    loss, g = pkg.model_grad("pwl", K, model, torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV))
+    torch.cuda.synchronize()
+    cl, cg = oracle.pwl_loss_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert rel_err(g.cpu().numpy(), cg) <= 1e-4
+    assert abs(float(loss.item()) - cl) <= 1e-4 * cl
+
+
+@pytest.mark.parametrize("npts", [1, 100, 50000])
+def test_mlp_gradient_matches_cpu(npts):
+    rng = np.random.default_rng(npts)
+    th = (0.3 * rng.standard_normal(oracle.MLP_PARAMS)).astype(np.float32)
+    x = rng.random(npts).astype(np.float32)
+    t = (x ** 2).astype(np.float32)
+    say("mlp grad", npts)
+    model = pkg.make_model("mlp", th)
+    loss, g = pkg.model_grad("mlp", 0, model, torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV))
+    torch.cuda.synchronize()
+    cl, cg = oracle.mlp_loss_grad(th.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert rel_err(g.cpu().numpy(), cg) <= 1e-4
+    assert abs(float(loss.item()) - cl) <= 1e-4 * cl
+
+
+def build(w, chunk=1024):
+    b = pkg.Builder(len(w), chunk, device=DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    p, a = b.build(wd)
+    torch.cuda.synchronize()
+    assert int(b.status.item()) == 0
+    return b, wd, p.cpu().numpy(), a.cpu().numpy()
+
+
+WEIGHTS = {
+    "lognormal": lambda n: inputs.lognormal(n, 2.0, 31),
+    "lognormal_sorted_desc": lambda n: inputs.sorted_descending(inputs.lognormal(n, 2.0, 31)),
+    "powerlaw": lambda n: inputs.power_law(n, 1.0, 31),
+}
+
+
+@pytest.mark.parametrize("kind,segments,epochs", [("pwl", 4096, 400), ("pwl", 256, 400),
+                                                  ("mlp", 0, 300)])
+@pytest.mark.parametrize("name", list(WEIGHTS))
+def test_learned_splits_are_exact(name, kind, segments, epochs):
+    n = (1 << 20) + 333
+    w = WEIGHTS[name](n)
+    say("learned", name, kind, segments)
+    b, wd, p0, a0 = build(w)
+    ref = b.intermediates()
+    model, loss = b.fit_split_model(kind, segments, epochs)
+    kind_, seg_, eps, npar = pkg.model_header(model)
+    assert kind_ == pkg.MODEL_KINDS[kind] and eps >= 1
+    b.resplit(model)
+    it = b.intermediates()
+    assert np.array_equal(it["split_i"], ref["split_i"])
+    assert np.array_equal(it["split_j"], ref["split_j"])
+    assert np.array_equal(it["spill"], ref["spill"])
+    # on the boundaries it was trained on the bracket always holds
+    assert it["header"].split_fallbacks == 0
+    # a full learned build writes the same table
+    b2 = pkg.Builder(n, 1024, "learned", model, device=DEV)
+    p2, a2 = b2.build(wd)
+    torch.cuda.synchronize()
+    assert int(b2.status.item()) == 0
+    assert np.array_equal(p2.cpu().numpy(), p0) and np.array_equal(a2.cpu().numpy(), a0)
+
+
+def test_trained_model_shrinks_the_search():
+    n = 1 << 22
+    w = WEIGHTS["lognormal"](n)
+    say("gain")
+    b, wd, _, _ = build(w)
+    it = b.intermediates()
+    model, loss = b.fit_split_model("pwl", 4096, 400)
+    _, _, eps, _ = pkg.model_header(model)
+    H = it["H"]
+    # binary search over the aggregate points visits ceil(log2(range + 1)) probes;
+    # the learned search visits 2 bracket checks + ceil(log2(2 eps + 1))
+    m = np.minimum(np.arange(len(it["split_j"]), dtype=np.int64) * 1024, n)
+    jlo = np.maximum(0, m - it["L"])
+    jhi = np.minimum(m, H)
+    rng_q = jhi // 64 - (jlo + 63) // 64 + 2
+    binary = np.ceil(np.log2(np.maximum(rng_q, 1))).mean()
+    learned = 2 + math.ceil(math.log2(2 * eps + 1))
+    print("eps", eps, "probes binary", binary, "learned", learned, "loss", float(loss.item()))
+    assert learned < binary
+
+
+@pytest.mark.parametrize("case", ["garbage", "wrong_kind", "short_blob", "untrained"])
+def test_bad_models_fall_back_and_stay_exact(case):
+    n = 300_000
+    w = WEIGHTS["lognormal_sorted_desc"](n)
+    say("bad model", case)
+    b, wd, p0, a0 = build(w)
+    ref = b.intermediates()
+    if case == "garbage":
+        model = pkg.make_model("pwl", np.full(65, 7.5, np.float32), segments=64, eps=0)
+    elif case == "wrong_kind":
+        model = pkg.make_model("pwl", np.zeros(65, np.float32), segments=64)
+        model[0] = 9
+    elif case == "short_blob":
+        model = pkg.make_model("mlp", np.zeros(1153, np.float32))[:400].clone()
+    else:
+        model, _ = b.fit_split_model("pwl", 64, 0)  # identity knots, never trained
+        b.build(wd)
+    b.resplit(model)
+    it = b.intermediates()
+    assert np.array_equal(it["split_j"], ref["split_j"])
+    assert np.array_equal(it["spill"], ref["spill"])
+    if case in ("garbage", "wrong_kind", "short_blob"):
+        assert it["header"].split_fallbacks > 0
