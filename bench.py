@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--layout", choices=["rows", "soa"], default="rows",
                     help="table as 16-byte rows (one gather per draw) or two arrays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-binary split comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-n", type=int, default=None,
@@ -105,6 +107,65 @@ def cpu_baseline(name, cpu_n, draws_sample):
         "host_cpu": _cpu_model(),
         "host_threads_available": os.cpu_count(),
     }
+
+
+def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
+    """Learned vs binary split on the 2^28 lognormal(0, 2) workload and its
+    sorted-descending variant: split-kernel time on the same partition
+    (alias_resplit), full build time, model fit time, fallbacks."""
+    import torch
+
+    name = "lognormal_2p28"
+    cfg = inputs.WORKLOADS[name]
+    n, chunk = cfg["n"], cfg["chunk"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w0 = torch.from_numpy(inputs.make_weights(name)).to(dev)
+    out = {"workload": name, "n": n, "chunk": chunk, "model": f"pwl{segments}",
+           "epochs": epochs}
+    rows = torch.empty((n, 4), dtype=torch.int32, device=dev)
+
+    def timed(fn, k):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(k):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / k
+
+    for variant in ("iid", "sorted_desc"):
+        w = w0 if variant == "iid" else torch.sort(w0, descending=True).values
+        b = pkg.Builder(n, chunk, device=dev)
+        b.build_rows(w, rows)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        model, loss = b.fit_split_model("pwl", segments, epochs)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        fit_ms = ev[0].elapsed_time(ev[1])
+        _, _, eps, _ = pkg.model_header(model)
+        t_bin = timed(lambda: b.resplit(None), reps)
+        t_lrn = timed(lambda: b.resplit(model), reps)
+        fallbacks = int(b.header().split_fallbacks)
+        bl = pkg.Builder(n, chunk, "learned", model, device=dev)
+        t_build_bin = timed(lambda: b.build_rows(w, rows), 5)
+        t_build_lrn = timed(lambda: bl.build_rows(w, rows), 5)
+        out[variant] = {
+            "fit_ms": round(fit_ms, 3), "final_loss": float(loss.item()), "eps": eps,
+            "split_ms_binary": round(t_bin, 4), "split_ms_learned": round(t_lrn, 4),
+            "split_speedup": round(t_bin / t_lrn, 3), "fallbacks": fallbacks,
+            "build_ms_binary": round(t_build_bin, 4), "build_ms_learned": round(t_build_lrn, 4),
+            "build_speedup": round(t_build_bin / t_build_lrn, 4),
+            "fit_amortised_after_builds": (round(fit_ms / (t_build_bin - t_build_lrn), 1)
+                                           if t_build_bin > t_build_lrn else None),
+        }
+        del b, bl
+        torch.cuda.empty_cache()
+    return out
 
 
 def _cpu_model():
@@ -249,6 +310,11 @@ def main():
         "samples_per_s": draws / (s_ms * 1e-3),
         "roofline": roof,
     }
+    if not args.no_learned:
+        print("[bench] learned vs binary split", file=sys.stderr, flush=True)
+        del w, out
+        torch.cuda.empty_cache()
+        result["learned_vs_binary"] = learned_vs_binary(pkg, inputs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_n, args.cpu_draws)

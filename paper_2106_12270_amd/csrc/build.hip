@@ -491,12 +491,29 @@ __device__ __forceinline__ uint64_t split_fine(const SplitCtx &c, int64_t qstar,
     g = sl + sh;
   }
   if (jb > jhi) jb = jhi;
+  // walk entry by entry; the weights are fetched 8 at a time so that one
+  // memory round trip serves 8 steps
   uint64_t j = ja;
-  while (j < jb) {
-    const dd g2 = add_d(add_d(g, c.h_w[j]), -c.l_w[c.m - j - 1]);
-    if (!le(g2, c.mavg)) break;
-    g = g2;
-    ++j;
+  bool stop = false;
+  while (!stop && j < jb) {
+    double hw[8], lw[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = j + u < jb;
+      hw[u] = in ? c.h_w[j + u] : 0.0;
+      lw[u] = in ? c.l_w[c.m - j - u - 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (stop || j >= jb) break;
+      const dd g2 = add_d(add_d(g, hw[u]), -lw[u]);
+      if (!le(g2, c.mavg)) {
+        stop = true;
+        break;
+      }
+      g = g2;
+      ++j;
+    }
   }
   *spill = (j < c.H) ? add_d(g, c.h_w[j]) - c.mavg : dd_make(0.0, 0.0);
   return j;
