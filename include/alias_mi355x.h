@@ -64,9 +64,13 @@ typedef struct alias_build_opts {
   uint32_t split_method;   /* ALIAS_SPLIT_* */
   const void *split_model; /* device pointer to a model blob written by
                               alias_split_model_fit() (learned method only) */
-  uint64_t split_model_bytes; /* size of that blob; the device ignores a model
-                                 whose declared parameters do not fit in it */
-  uint32_t reserved[2];    /* must be zero */
+  uint64_t split_model_bytes;  /* size of one model blob; the device ignores a
+                                  model whose declared parameters do not fit */
+  uint64_t split_model_stride; /* batched builds: bytes from one table's model
+                                  to the next; 0 = all tables share one model */
+  uint32_t pack_waves;     /* sections packed per block, 1..4; 0 = as many as
+                              the LDS allows (an autotuning knob) */
+  uint32_t reserved;       /* must be zero */
 } alias_build_opts;
 
 /* Device-side header at the start of a build workspace (read-only for the
@@ -164,6 +168,78 @@ int alias_sample(const double *d_prob, const uint32_t *d_alias, uint64_t n, uint
  * table.  d_rows: device, n rows, 16-byte aligned. */
 int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
                       uint64_t first_draw, uint32_t table_id, uint32_t *d_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched tables (an added system pattern: many independent distributions,
+ * e.g. one per graph vertex or per topic, the motivation of Sec. 1).  T
+ * tables of uneven sizes are stored back to back: table t owns items
+ * [offsets[t], offsets[t+1]) of the weight array and the same rows of the
+ * output table.  The whole batch is built by one fixed sequence of kernel
+ * launches on `stream` (no host synchronisation or readback, sizes derived
+ * on the device from the offsets), so a build followed by a batched sample
+ * can be captured into one HIP graph and replayed.  Each table's result is
+ * bit for bit the table that alias_build / alias_build_rows would write for
+ * that table alone with the same options.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of a batched build of T tables holding total_items items
+ * in all (T in [1, 2^20], total_items in [1, 2^40]); 0 if invalid. */
+size_t alias_build_batched_workspace_bytes(uint32_t T, uint64_t total_items,
+                                           const alias_build_opts *opts);
+
+/* Build T alias tables in one batch.
+ *   d_w         device, total_items doubles: all tables' weights, back to back.
+ *   d_offsets   device, T+1 uint64: offsets[0] = 0, nondecreasing,
+ *               offsets[T] = total_items (checked on the device).
+ *   d_prob, d_alias  device, total_items entries each; row offsets[t] + k
+ *               is row k of table t; aliases are table-local ids.
+ *   d_ws        device workspace of >= alias_build_batched_workspace_bytes()
+ *               bytes, 256-byte aligned.  Table t's header (alias_ws_header)
+ *               is the t-th entry of an array at the workspace start.
+ *   d_status    device, T int32: table t's status: ALIAS_OK, ALIAS_EWEIGHTS,
+ *               ALIAS_EINTERNAL, or ALIAS_EINVAL for an empty table (n_t = 0)
+ *               or one of more than 2^32 - 1 items (that table gets no rows)
+ *               and for every table when the offsets are inconsistent
+ *               (nothing is written then).
+ *   opts        as for alias_build; with the learned split, table t uses the
+ *               model blob at split_model + t * split_model_stride (stride 0:
+ *               one model for all tables).
+ * Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE, ALIAS_EMODEL or ALIAS_EHIP. */
+int alias_build_batched(const double *d_w, const uint64_t *d_offsets, uint32_t T,
+                        uint64_t total_items, double *d_prob, uint32_t *d_alias, void *d_ws,
+                        size_t ws_bytes, int32_t *d_status, const alias_build_opts *opts,
+                        void *stream);
+
+/* alias_build_batched writing 16-byte rows (layout as alias_build_rows);
+ * d_rows: device, total_items rows, 16-byte aligned. */
+int alias_build_batched_rows(const double *d_w, const uint64_t *d_offsets, uint32_t T,
+                             uint64_t total_items, void *d_rows, void *d_ws, size_t ws_bytes,
+                             int32_t *d_status, const alias_build_opts *opts, void *stream);
+
+/* Sample all tables of a batch in one launch.  Table t gets the draws
+ * [draw_offsets[t], draw_offsets[t+1]) of the output; its q-th draw is
+ * exactly alias_sample's draw q on that table alone with first_draw 0 and
+ * table_id t (so tables draw from independent Philox streams), and is
+ * written as a table-local item id.
+ *   d_offsets        device, T+1 uint64 (as for the build)
+ *   d_draw_offsets   device, T+1 uint64: draw_offsets[0] = 0, nondecreasing,
+ *                    draw_offsets[T] = total_draws
+ *   d_out            device, total_draws uint32
+ *   d_status         device int32: ALIAS_OK, or ALIAS_EINVAL if the offsets
+ *                    are inconsistent or a table with draws has no items or
+ *                    more than 2^32 - 1 (those draws are written as
+ *                    0xFFFFFFFF; no row outside the batch is read).
+ * Returns ALIAS_OK, ALIAS_EINVAL or ALIAS_EHIP. */
+int alias_sample_batched(const double *d_prob, const uint32_t *d_alias, const uint64_t *d_offsets,
+                         uint32_t T, uint64_t total_items, const uint64_t *d_draw_offsets,
+                         uint64_t total_draws, uint64_t seed, uint32_t *d_out,
+                         int32_t *d_status, void *stream);
+
+/* alias_sample_batched on a batch of 16-byte rows (same draws, bit for bit). */
+int alias_sample_batched_rows(const void *d_rows, const uint64_t *d_offsets, uint32_t T,
+                              uint64_t total_items, const uint64_t *d_draw_offsets,
+                              uint64_t total_draws, uint64_t seed, uint32_t *d_out,
+                              int32_t *d_status, void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned split predictor (an added system pattern; the paper's splits use

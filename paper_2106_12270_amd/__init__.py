@@ -12,6 +12,7 @@ import os
 __all__ = [
     "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
     "sample", "build_rows", "sample_rows", "rows_split", "Builder", "status_str",
+    "BatchBuilder", "sample_batched", "sample_batched_rows",
     "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
     "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
 ]
@@ -39,7 +40,9 @@ class BuildOpts(C.Structure):
         ("split_method", C.c_uint32),
         ("split_model", C.c_void_p),
         ("split_model_bytes", C.c_uint64),
-        ("reserved", C.c_uint32 * 2),
+        ("split_model_stride", C.c_uint64),
+        ("pack_waves", C.c_uint32),
+        ("reserved", C.c_uint32),
     ]
 
 
@@ -97,6 +100,18 @@ def lib():
         L.alias_split_model_grad.restype = C.c_int
         L.alias_resplit.argtypes = [vp, u64, C.POINTER(BuildOpts), vp]
         L.alias_resplit.restype = C.c_int
+        L.alias_build_batched_workspace_bytes.argtypes = [u32, u64, C.POINTER(BuildOpts)]
+        L.alias_build_batched_workspace_bytes.restype = C.c_size_t
+        L.alias_build_batched.argtypes = [vp, vp, u32, u64, vp, vp, vp, C.c_size_t, vp,
+                                          C.POINTER(BuildOpts), vp]
+        L.alias_build_batched.restype = C.c_int
+        L.alias_build_batched_rows.argtypes = [vp, vp, u32, u64, vp, vp, C.c_size_t, vp,
+                                               C.POINTER(BuildOpts), vp]
+        L.alias_build_batched_rows.restype = C.c_int
+        L.alias_sample_batched.argtypes = [vp, vp, vp, u32, u64, vp, u64, u64, vp, vp, vp]
+        L.alias_sample_batched.restype = C.c_int
+        L.alias_sample_batched_rows.argtypes = [vp, vp, u32, u64, vp, u64, u64, vp, vp, vp]
+        L.alias_sample_batched_rows.restype = C.c_int
         L.alias_status_str.argtypes = [C.c_int]
         L.alias_status_str.restype = C.c_char_p
         L.alias_version.argtypes = []
@@ -112,8 +127,10 @@ def status_str(code):
         return f"status {code}"
 
 
-def _opts(chunk=None, split="binary", model=None):
+def _opts(chunk=None, split="binary", model=None, model_stride=0, pack_waves=0):
     o = BuildOpts()
+    o.split_model_stride = int(model_stride)
+    o.pack_waves = int(pack_waves)
     o.chunk_items = 0 if chunk is None else int(chunk)
     if split in ("binary", SPLIT_BINARY):
         o.split_method = SPLIT_BINARY
@@ -408,3 +425,130 @@ def sample(prob, alias, count, seed, first_draw=0, table_id=0, out=None, stream=
     if st:
         raise AliasError(st, "alias_sample")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batched tables
+# ---------------------------------------------------------------------------
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class BatchBuilder:
+    """Owns the workspace and per-table status words for repeated builds of a
+    batch of T tables holding `total` items (layout given by device offsets).
+
+    model / model_stride select the learned split: table t uses the blob at
+    byte model_stride * t of `model` (stride 0: one shared model)."""
+
+    def __init__(self, T, total, chunk=None, split="binary", model=None, model_stride=0,
+                 pack_waves=0, device="cuda"):
+        import torch
+
+        self.T = int(T)
+        self.total = int(total)
+        self.chunk = chunk
+        self.model = model
+        self.opts = _opts(chunk, split, model, model_stride, pack_waves)
+        if model is not None and model_stride:
+            self.opts.split_model_bytes = int(model_stride)
+        b = lib().alias_build_batched_workspace_bytes(self.T, self.total, C.byref(self.opts))
+        if b == 0:
+            raise AliasError(ALIAS_EINVAL, "alias_build_batched_workspace_bytes")
+        self.ws_bytes = b
+        self.ws = torch.empty(b, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(self.T, dtype=torch.int32, device=device)
+
+    def _check(self, w, offsets):
+        import torch
+
+        _check_dev(w, torch.float64, "w")
+        _check_dev(offsets, torch.int64, "offsets")
+        if w.numel() != self.total or offsets.numel() != self.T + 1:
+            raise ValueError("w / offsets do not match this batch")
+
+    def build(self, w, offsets, prob=None, alias=None, stream=None):
+        import torch
+
+        self._check(w, offsets)
+        if prob is None:
+            prob = torch.empty(self.total, dtype=torch.float64, device=w.device)
+        if alias is None:
+            alias = torch.empty(self.total, dtype=torch.int32, device=w.device)
+        _check_dev(prob, torch.float64, "prob")
+        _check_dev(alias, torch.int32, "alias")
+        st = lib().alias_build_batched(_ptr(w), _ptr(offsets), self.T, self.total, _ptr(prob),
+                                       _ptr(alias), _ptr(self.ws), self.ws_bytes,
+                                       _ptr(self.status), C.byref(self.opts), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_build_batched")
+        return prob, alias
+
+    def build_rows(self, w, offsets, rows=None, stream=None):
+        import torch
+
+        self._check(w, offsets)
+        if rows is None:
+            rows = torch.empty((self.total, 4), dtype=torch.int32, device=w.device)
+        _check_rows(rows, self.total)
+        st = lib().alias_build_batched_rows(_ptr(w), _ptr(offsets), self.T, self.total,
+                                            _ptr(rows), _ptr(self.ws), self.ws_bytes,
+                                            _ptr(self.status), C.byref(self.opts),
+                                            _stream(stream))
+        if st:
+            raise AliasError(st, "alias_build_batched_rows")
+        return rows
+
+    def headers(self):
+        """Per-table workspace headers of the last build (synchronises)."""
+        sz = C.sizeof(WsHeader)
+        raw = self.ws[: sz * self.T].cpu().numpy().tobytes()
+        return [WsHeader.from_buffer_copy(raw[t * sz:(t + 1) * sz]) for t in range(self.T)]
+
+
+def _sample_batched_args(offsets, draw_offsets, total_items, out, status, device):
+    import torch
+
+    _check_dev(offsets, torch.int64, "offsets")
+    _check_dev(draw_offsets, torch.int64, "draw_offsets")
+    T = offsets.numel() - 1
+    if draw_offsets.numel() != T + 1:
+        raise ValueError("draw_offsets must have T+1 entries")
+    if out is None:
+        raise ValueError("out (int32, total_draws entries) is required")
+    _check_dev(out, torch.int32, "out")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=device)
+    _check_dev(status, torch.int32, "status")
+    return T, status
+
+
+def sample_batched(prob, alias, offsets, draw_offsets, seed, out, status=None, stream=None):
+    """Draw out.numel() samples over a batch: table t fills
+    out[draw_offsets[t]:draw_offsets[t+1]] with table-local ids.  Returns
+    (out, status) where status is a 1-element int32 device tensor."""
+    import torch
+
+    _check_dev(prob, torch.float64, "prob")
+    _check_dev(alias, torch.int32, "alias")
+    T, status = _sample_batched_args(offsets, draw_offsets, prob.numel(), out, status, prob.device)
+    st = lib().alias_sample_batched(_ptr(prob), _ptr(alias), _ptr(offsets), T, prob.numel(),
+                                    _ptr(draw_offsets), out.numel(), int(seed) & (2**64 - 1),
+                                    _ptr(out), _ptr(status), _stream(stream))
+    if st:
+        raise AliasError(st, "alias_sample_batched")
+    return out, status
+
+
+def sample_batched_rows(rows, offsets, draw_offsets, seed, out, status=None, stream=None):
+    """sample_batched on a batch of 16-byte rows (the same draws)."""
+    _check_rows(rows, rows.shape[0])
+    T, status = _sample_batched_args(offsets, draw_offsets, rows.shape[0], out, status,
+                                     rows.device)
+    st = lib().alias_sample_batched_rows(_ptr(rows), _ptr(offsets), T, rows.shape[0],
+                                         _ptr(draw_offsets), out.numel(),
+                                         int(seed) & (2**64 - 1), _ptr(out), _ptr(status),
+                                         _stream(stream))
+    if st:
+        raise AliasError(st, "alias_sample_batched_rows")
+    return out, status

@@ -49,64 +49,83 @@ struct ReducePart {
   double pad2;
 };
 
+// Workspace layout of a build of T tables holding `total` items in all
+// (one table: T = 1, total = n; the first table header sits at offset 0).
 struct Layout {
-  alias_ws_layout pub;
-  uint64_t parts;      // ReducePart[reduce_blocks]
-  uint64_t tilesum;    // TileSum per tile
-  uint64_t tilepre;    // TilePrefix per tile, within its group of 1024 tiles
-  uint64_t grpsum;     // TileSum per group of 1024 tiles
-  uint64_t grppre;     // TilePrefix per group
-  uint32_t chunk;
+  alias_ws_layout pub;  // offsets of the arrays shared with the public view
+  uint64_t tile_start;  // uint64[T+1]: first tile of each table
+  uint64_t sec_start;   // uint64[T+1]: first section of each table
+  uint64_t tilew;       // ReducePart per tile
+  uint64_t tilesum;     // TileSum per tile
+  uint64_t tilepre;     // TilePrefix per tile (within its table)
+  uint64_t grp;         // setup scratch: uint64[2 * groups]
+  uint64_t flags;       // uint32[16]: [0] = inconsistent batch description
+  uint64_t tiles_max, secs_max, total;
+  uint32_t T, chunk, pack_waves;
 };
+
+constexpr uint32_t kMaxTables = 1u << 20;
+constexpr int kSetupGroup = 1024;
 
 __host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 // Computes the workspace layout; returns false for invalid arguments.
-inline bool compute_layout(uint64_t n, const alias_build_opts *o, Layout *L) {
-  if (n == 0 || n > 0xFFFFFFFFull) return false;
-  uint32_t chunk = kDefaultChunk;
+inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_opts *o, Layout *L) {
+  if (T == 0 || T > kMaxTables || total == 0 || total > (1ull << 40)) return false;
+  uint32_t chunk = kDefaultChunk, waves = 0;
   if (o) {
     if (o->chunk_items) chunk = o->chunk_items;
     if (o->split_method > ALIAS_SPLIT_LEARNED) return false;
-    for (int r = 0; r < 2; ++r)
-      if (o->reserved[r]) return false;
+    if (o->pack_waves > (uint32_t)kPackWaves) return false;
+    waves = o->pack_waves;
+    if (o->reserved) return false;
   }
   if (chunk < kMinChunk || chunk > kMaxChunk || (chunk & (chunk - 1))) return false;
-  const uint64_t tiles = (n + kTileItems - 1) / kTileItems;
-  const uint64_t s = (n + chunk - 1) / chunk;
-  uint64_t rb = (n + (uint64_t)kReduceThreads * 16 - 1) / ((uint64_t)kReduceThreads * 16);
-  if (rb > (uint64_t)kReduceMaxBlocks) rb = kReduceMaxBlocks;
-  if (rb == 0) rb = 1;
-  const uint64_t nagg = n / kAggStride + 2;
+  const uint64_t tiles = (total + kTileItems - 1) / kTileItems + T;
+  // section boundaries: sum over tables of (ceil(n_t / C) + 1) <= total/C + 2T
+  const uint64_t secs = (total + chunk - 1) / chunk + 2ull * T;
+  const uint64_t groups = (T + kSetupGroup - 1) / kSetupGroup;
+  const uint64_t nagg = total / kAggStride + 2ull * T + 2;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     uint64_t at = off;
     off = align256(off + bytes);
     return at;
   };
-  L->pub.header = take(sizeof(alias_ws_header));
-  L->parts = take(rb * sizeof(ReducePart));
-  const uint64_t groups = (tiles + kScanGroup - 1) / kScanGroup;
+  L->pub.header = take((uint64_t)T * sizeof(alias_ws_header));
+  L->tile_start = take((T + 1ull) * 8);
+  L->sec_start = take((T + 1ull) * 8);
+  L->flags = take(64);
+  L->grp = take(groups * 16 + 16);
+  L->tilew = take(tiles * sizeof(ReducePart));
   L->tilesum = take(tiles * sizeof(TileSum));
   L->tilepre = take(tiles * sizeof(TilePrefix));
-  L->grpsum = take(groups * sizeof(TileSum));
-  L->grppre = take(groups * sizeof(TilePrefix));
-  L->pub.l_idx = take(n * 4);
-  L->pub.h_idx = take(n * 4);
-  L->pub.l_w = take(n * 8);
-  L->pub.h_w = take(n * 8);
+  L->pub.l_idx = take(total * 4);
+  L->pub.h_idx = take(total * 4);
+  L->pub.l_w = take(total * 8);
+  L->pub.h_w = take(total * 8);
   L->pub.agg_l = take(nagg * 16);
   L->pub.agg_h = take(nagg * 16);
-  L->pub.split_i = take((s + 1) * 4);
-  L->pub.split_j = take((s + 1) * 4);
-  L->pub.spill = take((s + 1) * 16);
+  L->pub.split_i = take(secs * 4);
+  L->pub.split_j = take(secs * 4);
+  L->pub.spill = take(secs * 16);
   L->pub.total_bytes = off;
-  L->pub.sections = (uint32_t)s;
+  L->pub.sections = (uint32_t)((total + chunk - 1) / chunk);
   L->pub.agg_stride = kAggStride;
-  L->pub.tiles = (uint32_t)tiles;
-  L->pub.reduce_blocks = (uint32_t)rb;
+  L->pub.tiles = (uint32_t)((total + kTileItems - 1) / kTileItems);
+  L->pub.reduce_blocks = L->pub.tiles;
+  L->tiles_max = tiles;
+  L->secs_max = secs;
+  L->total = total;
+  L->T = T;
   L->chunk = chunk;
+  L->pack_waves = waves;
   return true;
+}
+
+inline bool compute_layout(uint64_t n, const alias_build_opts *o, Layout *L) {
+  if (n == 0 || n > 0xFFFFFFFFull) return false;
+  return compute_layout_batch(1, n, o, L);
 }
 
 // ---------------------------------------------------------------------------

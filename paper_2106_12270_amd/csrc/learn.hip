@@ -397,8 +397,9 @@ static int launch_grad(uint32_t kind, const SplitModel *M, const float *x, const
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 
-int launch_split_only(void *d_ws, uint64_t n, const Layout &Lo, const SplitModel *model,
-                      uint64_t model_bytes, hipStream_t st);
+int launch_split_only(void *d_ws, const uint64_t *d_offsets, uint64_t n1, const Layout &Lo,
+                      const unsigned char *models, uint64_t model_bytes, uint64_t model_stride,
+                      hipStream_t st);
 
 }  // namespace amdalias
 
@@ -501,7 +502,8 @@ int alias_resplit(void *d_ws, uint64_t n, const alias_build_opts *opts, void *st
     model = (const SplitModel *)opts->split_model;
     model_bytes = opts->split_model_bytes;
   }
-  return launch_split_only(d_ws, n, L, model, model_bytes, (hipStream_t)stream);
+  return launch_split_only(d_ws, nullptr, n, L, (const unsigned char *)model, model_bytes, 0,
+                           (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -116,4 +116,108 @@ int launch_sample_rows(const TableRow *rows, uint64_t n, uint64_t count, uint64_
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched sampling: T tables back to back (table t owns rows
+// [offsets[t], offsets[t+1])); draws [draw_off[t], draw_off[t+1]) belong to
+// table t.  Draw d of table t is that table's draw q = d - draw_off[t], made
+// exactly as a single-table call with first_draw 0 and table id t would make
+// it; the output is the table-local item id.  Draws are handed out in
+// contiguous chunks so that a block's draws mostly fall in one table whose
+// rows stay in L2.
+// ---------------------------------------------------------------------------
+constexpr int kBatchPer = 4;  // draws per thread per chunk
+constexpr int kBatchChunk = kSampleThreads * kBatchPer;
+
+// largest t in [0, T) with start[t] <= x
+__device__ __forceinline__ uint32_t find_first_le(const uint64_t *start, uint32_t T, uint64_t x) {
+  uint32_t lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (start[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <bool kRows>
+__global__ __launch_bounds__(kSampleThreads) void k_sample_batched(
+    const double *__restrict__ prob, const uint32_t *__restrict__ alias,
+    const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets,
+    const uint64_t *__restrict__ draw_off, uint32_t T, uint64_t total_items, uint64_t total_draws,
+    uint32_t k0, uint32_t k1, uint32_t *__restrict__ out, int32_t *status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const bool ok = draw_off[0] == 0 && draw_off[T] == total_draws && offsets[0] == 0 &&
+                    offsets[T] == total_items;
+    if (!ok) *status = ALIAS_EINVAL;
+  }
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kBatchChunk; c0 < total_draws;
+       c0 += (uint64_t)gridDim.x * kBatchChunk) {
+    uint32_t t = find_first_le(draw_off, T, c0);
+    uint64_t d[kBatchPer], row[kBatchPer], base[kBatchPer];
+    double coin[kBatchPer];
+    bool live[kBatchPer];
+#pragma unroll
+    for (int u = 0; u < kBatchPer; ++u) {
+      d[u] = c0 + (uint64_t)u * kSampleThreads + threadIdx.x;
+      live[u] = d[u] < total_draws;
+      while (t + 1 < T && draw_off[t + 1] <= d[u]) ++t;
+      const uint64_t a = offsets[t], b = offsets[t + 1];
+      const uint64_t n = b - a;
+      // an empty, oversized or out-of-range table gets no row reads
+      if (live[u] && (b < a || b > total_items || n == 0 || n > 0xFFFFFFFFull ||
+                      d[u] < draw_off[t])) {
+        out[d[u]] = 0xFFFFFFFFu;
+        *status = ALIAS_EINVAL;
+        live[u] = false;
+      }
+      base[u] = a;
+      if (live[u]) draw_setup(d[u] - draw_off[t], t, k0, k1, n, row[u], coin[u]);
+    }
+    if (kRows) {
+      TableRow r[kBatchPer];
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u)
+        if (live[u]) r[u] = rows[base[u] + row[u]];
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u)
+        if (live[u]) out[d[u]] = (coin[u] < r[u].prob) ? (uint32_t)row[u] : r[u].alias;
+    } else {
+      double p[kBatchPer];
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u)
+        if (live[u]) p[u] = prob[base[u] + row[u]];
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u)
+        if (live[u])
+          out[d[u]] = (coin[u] < p[u]) ? (uint32_t)row[u] : alias[base[u] + row[u]];
+    }
+  }
+}
+
+__global__ void k_set_status(int32_t *status, int32_t v) {
+  if (threadIdx.x == 0) *status = v;
+}
+
+int launch_sample_batched(const double *prob, const uint32_t *alias, const TableRow *rows,
+                          const uint64_t *offsets, const uint64_t *draw_off, uint32_t T,
+                          uint64_t total_items, uint64_t total_draws, uint64_t seed,
+                          uint32_t *out, int32_t *status, hipStream_t st) {
+  uint64_t blocks = (total_draws + kBatchChunk - 1) / kBatchChunk;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, st, status, (int32_t)ALIAS_OK);
+  if (rows)
+    hipLaunchKernelGGL(k_sample_batched<true>, dim3((uint32_t)blocks), dim3(kSampleThreads), 0, st,
+                       nullptr, nullptr, rows, offsets, draw_off, T, total_items, total_draws,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), out, status);
+  else
+    hipLaunchKernelGGL(k_sample_batched<false>, dim3((uint32_t)blocks), dim3(kSampleThreads), 0,
+                       st, prob, alias, nullptr, offsets, draw_off, T, total_items, total_draws,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), out, status);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
 }  // namespace amdalias

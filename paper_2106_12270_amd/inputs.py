@@ -151,3 +151,21 @@ def make_weights(name: str, n: int = None) -> np.ndarray:
     if cfg["dist"] == "lognormal":
         return lognormal(n, cfg["sigma"], seed)
     raise KeyError(name)
+
+
+def make_batch(name: str, tables: int = None, draws: int = None):
+    """A batched workload (optionally with fewer tables or draws, same recipe):
+    (weights, offsets[T+1], draw_offsets[T+1]), offsets as uint64.  Draws are
+    apportioned to the tables proportionally to their sizes."""
+    cfg = WORKLOADS[name]
+    T = cfg["tables"] if tables is None else int(tables)
+    seed = weight_seed(cfg["key"])
+    sizes = log_uniform_sizes(T, cfg["lo"], cfg["hi"], seed)
+    if cfg["dist"] == "lognormal":
+        w = batch_lognormal(sizes, seed + 1, cfg["sigma"])
+    elif cfg["dist"] == "zipf":
+        w, _ = batch_zipf(sizes, seed + 1)
+    else:
+        raise KeyError(name)
+    total_draws = cfg["draws"] if draws is None else int(draws)
+    return w, offsets_from_sizes(sizes), offsets_from_sizes(apportion(total_draws, sizes))

@@ -93,7 +93,7 @@ def test_build_rejects_bad_arguments_before_launching():
     o3.split_method = 7
     assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o3), None) == pkg.ALIAS_EINVAL
     o4 = pkg.BuildOpts()
-    o4.reserved[1] = 1
+    o4.reserved = 1
     assert L.alias_build(fake, n, fake, fake, fake, wsb, fake, C.byref(o4), None) == pkg.ALIAS_EINVAL
     # learned split without a model
     o5 = pkg.BuildOpts()
@@ -131,6 +131,55 @@ def test_sample_rejects_bad_arguments_before_launching():
     assert L.alias_sample(fake, fake, 10, 10, 1, 2**64 - 5, 0, fake, None) == pkg.ALIAS_EINVAL
     # zero draws: nothing to do, nothing launched
     assert L.alias_sample(fake, fake, 10, 0, 1, 0, 0, fake, None) == pkg.ALIAS_OK
+
+
+def test_batched_workspace_and_layout_rules():
+    L = pkg.lib()
+    o = pkg.BuildOpts()
+    one = L.alias_build_batched_workspace_bytes(1, 5000, C.byref(o))
+    assert one == pkg.workspace_bytes(5000)  # a batch of one table is the plain build
+    many = L.alias_build_batched_workspace_bytes(100_000, 788_000_000, C.byref(o))
+    assert 0 < many < 26 * 788_000_000 + (1 << 26)
+    assert L.alias_build_batched_workspace_bytes(0, 100, C.byref(o)) == 0
+    assert L.alias_build_batched_workspace_bytes((1 << 20) + 1, 1 << 22, C.byref(o)) == 0
+    assert L.alias_build_batched_workspace_bytes(10, 0, C.byref(o)) == 0
+    o.pack_waves = 5
+    assert L.alias_build_batched_workspace_bytes(10, 100, C.byref(o)) == 0
+
+
+def test_batched_entry_points_reject_bad_arguments_before_launching():
+    L = pkg.lib()
+    o = pkg.BuildOpts()
+    T, total = 10, 5000
+    wsb = L.alias_build_batched_workspace_bytes(T, total, C.byref(o))
+    fake = C.c_void_p(0x10000)
+    f8 = C.c_void_p(0x10008)
+    bb = L.alias_build_batched
+    assert bb(None, fake, T, total, fake, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert bb(fake, None, T, total, fake, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert bb(fake, fake, 0, total, fake, fake, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert bb(fake, fake, T, total, fake, fake, f8, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert bb(fake, fake, T, total, fake, fake, fake, wsb - 1, fake, C.byref(o),
+              None) == pkg.ALIAS_EWORKSPACE
+    o5 = pkg.BuildOpts()
+    o5.split_method = pkg.SPLIT_LEARNED
+    o5.split_model = 0x10000
+    o5.split_model_bytes = 64
+    o5.split_model_stride = 32  # smaller than one blob
+    assert bb(fake, fake, T, total, fake, fake, fake, wsb, fake, C.byref(o5),
+              None) == pkg.ALIAS_EMODEL
+    br = L.alias_build_batched_rows
+    assert br(fake, fake, T, total, f8, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    assert br(fake, fake, T, total, None, fake, wsb, fake, C.byref(o), None) == pkg.ALIAS_EINVAL
+    sb = L.alias_sample_batched
+    assert sb(fake, fake, fake, 0, total, fake, 100, 1, fake, fake, None) == pkg.ALIAS_EINVAL
+    assert sb(fake, fake, None, T, total, fake, 100, 1, fake, fake, None) == pkg.ALIAS_EINVAL
+    assert sb(fake, fake, fake, T, total, None, 100, 1, fake, fake, None) == pkg.ALIAS_EINVAL
+    assert sb(fake, fake, fake, T, total, fake, 100, 1, fake, None, None) == pkg.ALIAS_EINVAL
+    assert sb(fake, fake, fake, T, 0, fake, 100, 1, fake, fake, None) == pkg.ALIAS_EINVAL
+    sr = L.alias_sample_batched_rows
+    assert sr(f8, fake, T, total, fake, 100, 1, fake, fake, None) == pkg.ALIAS_EINVAL
+    assert sr(fake, fake, T, total, fake, 100, 1, None, fake, None) == pkg.ALIAS_EINVAL
 
 
 def test_product_package_does_not_use_the_oracle():

@@ -1,0 +1,321 @@
+"""GPU parity of the batched path: many tables of uneven sizes built and
+sampled in one launch sequence (through the C ABI).
+
+Bars, per table:
+- exact-arithmetic inputs: the table equals the oracle's sequential PSA bit
+  for bit;
+- general inputs: the table equals the single-table GPU build bit for bit
+  (which the single-table tests pin to the oracle), aliases equal the
+  oracle's, probabilities within 2 ulp, mass invariant within 1e-12;
+- samples: table t's draws equal the oracle's draws on that table with
+  first draw 0 and table id t, bit for bit;
+- a HIP graph holding build + sample replays to the eager results, also
+  after the inputs change between replays.
+Paper: arXiv 2106.12270 (Sec. 2.2, Sec. 4, Sec. 5).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_2106_12270_amd as pkg
+from paper_2106_12270_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.lib()
+    oracle.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev_u64(a):
+    return torch.from_numpy(np.asarray(a, dtype=np.uint64).view(np.int64)).to(DEV)
+
+
+def batched_build(w, off, chunk=None, rows=False, **kw):
+    T = len(off) - 1
+    bb = pkg.BatchBuilder(T, len(w), chunk, device=DEV, **kw)
+    wd = torch.from_numpy(np.ascontiguousarray(w)).to(DEV)
+    od = dev_u64(off)
+    if rows:
+        r = bb.build_rows(wd, od)
+        torch.cuda.synchronize()
+        p, a = pkg.rows_split(r)
+        return bb, bb.status.cpu().numpy(), p.cpu().numpy(), a.cpu().numpy().view(np.uint32), r
+    p, a = bb.build(wd, od)
+    torch.cuda.synchronize()
+    return bb, bb.status.cpu().numpy(), p.cpu().numpy(), a.cpu().numpy().view(np.uint32)
+
+
+def ulp_diff(a, b):
+    return np.abs(a.view(np.int64) - b.view(np.int64))
+
+
+EXACT_SIZES = [1, 2, 63, 64, 65, 1000, 4095, 4096, 4097, 3 * 4096 + 77, 20000, 1, 7]
+
+
+@pytest.mark.parametrize("chunk", [64, 1024])
+def test_exact_batch_bitwise(chunk):
+    parts = [inputs.exact_integers(n, seed=1000 + k, zero_frac=0.05)
+             for k, n in enumerate(EXACT_SIZES)]
+    w = np.concatenate(parts)
+    off = inputs.offsets_from_sizes(EXACT_SIZES)
+    say("batched exact", chunk)
+    bb, st, p, a = batched_build(w, off, chunk)
+    assert (st == pkg.ALIAS_OK).all(), st
+    for t, wt in enumerate(parts):
+        s, e = int(off[t]), int(off[t + 1])
+        op, oa = oracle.psa_build(wt, chunk=chunk)
+        assert np.array_equal(a[s:e], oa), t
+        assert np.array_equal(p[s:e], op), t
+    hdr = bb.headers()
+    for t, wt in enumerate(parts):
+        tot = oracle.total(wt)
+        assert hdr[t].avg_hi + hdr[t].avg_lo == tot[2] + tot[3]
+
+
+def test_general_batch_matches_single_builds_and_oracle():
+    sizes = inputs.log_uniform_sizes(300, 16, 1 << 15, seed=77)
+    w = inputs.batch_lognormal(sizes, seed=78, sigma=2.0)
+    off = inputs.offsets_from_sizes(sizes)
+    say("batched general", len(sizes), len(w))
+    bb, st, p, a = batched_build(w, off, 1024)
+    assert (st == pkg.ALIAS_OK).all()
+    for t in range(len(sizes)):
+        s, e = int(off[t]), int(off[t + 1])
+        wt = w[s:e]
+        if t % 10 == 0:  # single-table GPU builds: bitwise
+            sp, sa = pkg.build(torch.from_numpy(wt).to(DEV), chunk=1024)
+            assert np.array_equal(p[s:e], sp.cpu().numpy()), t
+            assert np.array_equal(a[s:e], sa.cpu().numpy().view(np.uint32)), t
+        op, oa = oracle.psa_build(wt, chunk=1024)
+        assert np.array_equal(a[s:e], oa), t
+        assert ulp_diff(p[s:e], op).max() <= 2, t
+        r = oracle.check(wt, p[s:e], a[s:e])
+        assert r["max_rel"] <= 1e-12 and r["zero_violations"] == 0, (t, r)
+
+
+def test_batch_rows_equal_two_array_layout():
+    sizes = inputs.log_uniform_sizes(200, 16, 70000, seed=5)
+    w, _ = inputs.batch_zipf(sizes, seed=6)
+    off = inputs.offsets_from_sizes(sizes)
+    say("batched rows")
+    _, st1, p1, a1 = batched_build(w, off, 512)
+    _, st2, p2, a2, _ = batched_build(w, off, 512, rows=True)
+    assert (st1 == 0).all() and (st2 == 0).all()
+    assert np.array_equal(p1, p2) and np.array_equal(a1, a2)
+
+
+def test_batch_status_per_table():
+    # an empty table and a table with a negative weight: only they fail
+    sizes = [100, 0, 5000, 300, 1]
+    w = inputs.lognormal(int(sum(sizes)), 1.0, 3)
+    w[100 + 0 + 17] = -1.0  # table 2
+    off = inputs.offsets_from_sizes(sizes)
+    say("batched status")
+    bb, st, p, a = batched_build(w, off, 1024)
+    assert list(st) == [pkg.ALIAS_OK, pkg.ALIAS_EINVAL, pkg.ALIAS_EWEIGHTS, pkg.ALIAS_OK,
+                        pkg.ALIAS_OK]
+    for t in (0, 3, 4):
+        s, e = int(off[t]), int(off[t + 1])
+        op, oa = oracle.psa_build(w[s:e], chunk=1024)
+        assert np.array_equal(a[s:e], oa)
+
+
+def test_batch_inconsistent_offsets_fail_every_table():
+    sizes = [100, 200, 300]
+    w = inputs.uniform01(600, 1)
+    off = inputs.offsets_from_sizes(sizes)
+    off[3] = 599  # does not end at total_items
+    say("batched bad offsets")
+    bb, st, _, _ = batched_build(w, off, 1024)
+    assert (st == pkg.ALIAS_EINVAL).all()
+    off = inputs.offsets_from_sizes(sizes)
+    off[1], off[2] = 400, 100  # decreasing
+    bb, st, _, _ = batched_build(w, off, 1024)
+    assert (st == pkg.ALIAS_EINVAL).all()
+
+
+@pytest.mark.parametrize("rows", [False, True])
+def test_batched_samples_bit_exact(rows):
+    sizes = np.array([1, 5, 4096, 77, 30000, 64, 2, 9000], dtype=np.int64)
+    w = inputs.batch_lognormal(sizes, seed=9, sigma=1.5)
+    off = inputs.offsets_from_sizes(sizes)
+    draws = inputs.apportion(300_001, sizes)
+    draws[1] = 0  # a table with no draws
+    doff = inputs.offsets_from_sizes(draws)
+    total = int(doff[-1])
+    say("batched samples", rows)
+    res = batched_build(w, off, 256, rows=rows)
+    st, p, a = res[1], res[2], res[3]
+    assert (st == 0).all()
+    out = torch.full((total,), -7, dtype=torch.int32, device=DEV)
+    seed = inputs.SAMPLE_SEED + 3
+    if rows:
+        out, sst = pkg.sample_batched_rows(res[4], dev_u64(off), dev_u64(doff), seed, out)
+    else:
+        out, sst = pkg.sample_batched(torch.from_numpy(p).to(DEV),
+                                      torch.from_numpy(a.view(np.int32)).to(DEV), dev_u64(off),
+                                      dev_u64(doff), seed, out)
+    torch.cuda.synchronize()
+    assert int(sst.item()) == 0
+    got = out.cpu().numpy().view(np.uint32)
+    for t in range(len(sizes)):
+        s, e = int(off[t]), int(off[t + 1])
+        ds, de = int(doff[t]), int(doff[t + 1])
+        ref = oracle.sample(p[s:e], a[s:e], de - ds, seed, first=0, table=t)
+        assert np.array_equal(got[ds:de], ref), t
+
+
+def test_batched_sampler_rejects_bad_offsets():
+    sizes = [10, 0, 20]
+    w = inputs.uniform01(30, 2)
+    off = inputs.offsets_from_sizes(sizes)
+    res = batched_build(w, off, 64)
+    p, a = res[2], res[3]
+    draws = np.array([5, 3, 4])  # table 1 is empty but gets draws
+    doff = inputs.offsets_from_sizes(draws)
+    out = torch.zeros(12, dtype=torch.int32, device=DEV)
+    say("batched sampler bad")
+    out, sst = pkg.sample_batched(torch.from_numpy(p).to(DEV),
+                                  torch.from_numpy(a.view(np.int32)).to(DEV), dev_u64(off),
+                                  dev_u64(doff), 1, out)
+    torch.cuda.synchronize()
+    assert int(sst.item()) == pkg.ALIAS_EINVAL
+    got = out.cpu().numpy().view(np.uint32)
+    assert (got[5:8] == 0xFFFFFFFF).all()
+    for t, (ds, de) in ((0, (0, 5)), (2, (8, 12))):
+        s, e = int(off[t]), int(off[t + 1])
+        assert np.array_equal(got[ds:de], oracle.sample(p[s:e], a[s:e], de - ds, 1, 0, t))
+
+
+def test_graph_capture_build_and_sample_replays():
+    sizes = inputs.log_uniform_sizes(500, 16, 20000, seed=21)
+    w1 = inputs.batch_lognormal(sizes, seed=22)
+    w2, _ = inputs.batch_zipf(sizes, seed=23)
+    off = inputs.offsets_from_sizes(sizes)
+    doff = inputs.offsets_from_sizes(inputs.apportion(1 << 20, sizes))
+    T, total, nd = len(sizes), len(w1), int(doff[-1])
+    say("graph capture", T, total, nd)
+    bb = pkg.BatchBuilder(T, total, 1024, device=DEV)
+    wd = torch.from_numpy(w1).to(DEV)
+    od, dd_ = dev_u64(off), dev_u64(doff)
+    rows = torch.empty((total, 4), dtype=torch.int32, device=DEV)
+    out = torch.empty(nd, dtype=torch.int32, device=DEV)
+    sst = torch.zeros(1, dtype=torch.int32, device=DEV)
+    seed = 12345
+
+    def step():
+        bb.build_rows(wd, od, rows=rows)
+        pkg.sample_batched_rows(rows, od, dd_, seed, out, status=sst)
+
+    # eager references for both weight sets
+    refs = []
+    for w in (w1, w2):
+        wd.copy_(torch.from_numpy(w))
+        step()
+        torch.cuda.synchronize()
+        refs.append((rows.clone(), out.clone()))
+    wd.copy_(torch.from_numpy(w1))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for k, which in enumerate((0, 1, 1, 0)):
+        rows.fill_(-1)
+        out.fill_(-1)
+        bb.status.fill_(99)
+        wd.copy_(torch.from_numpy((w1, w2)[which]))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (bb.status == 0).all(), k
+        assert int(sst.item()) == 0
+        assert torch.equal(rows, refs[which][0]), k
+        assert torch.equal(out, refs[which][1]), k
+        _ = (out.float().sum() + 1).item()  # eager work between replays
+
+
+def test_learned_split_per_table_models():
+    sizes = [70000, 300000, 5000, 150000]
+    w = inputs.batch_lognormal(sizes, seed=31, sigma=2.0)
+    off = inputs.offsets_from_sizes(sizes)
+    say("batched learned")
+    _, st0, p0, a0 = batched_build(w, off, 1024)
+    blobs = []
+    for t in range(len(sizes)):
+        s, e = int(off[t]), int(off[t + 1])
+        b = pkg.Builder(e - s, 1024, device=DEV)
+        b.build(torch.from_numpy(w[s:e]).to(DEV))
+        m, _ = b.fit_split_model("pwl", 256, 200)
+        blobs.append(m)
+    stride = max(int(m.numel()) for m in blobs)
+    stride = (stride + 15) // 16 * 16
+    models = torch.zeros(stride * len(sizes), dtype=torch.uint8, device=DEV)
+    for t, m in enumerate(blobs):
+        models[t * stride:t * stride + m.numel()] = m
+    bb, st, p, a = batched_build(w, off, 1024, split="learned", model=models, model_stride=stride)
+    assert (st == 0).all()
+    assert np.array_equal(p, p0) and np.array_equal(a, a0)
+    assert all(h.split_fallbacks == 0 for h in bb.headers())
+    # one shared model that fits none of the tables: fallbacks, same tables
+    bb, st, p, a = batched_build(w, off, 1024, split="learned", model=blobs[2])
+    assert np.array_equal(p, p0) and np.array_equal(a, a0)
+
+
+@pytest.mark.parametrize("name", ["batch_100k_16_65536", "batch_1024_2p14_2p22"])
+def test_full_size_batches_sampled_tables(name):
+    """The batched workloads at full size: sampled tables against the oracle
+    (invariant, aliases, 2 ulp) and their draws bit-exact."""
+    say("full batch", name, "generating")
+    w, off, doff = inputs.make_batch(name)
+    T, total, nd = len(off) - 1, len(w), int(doff[-1])
+    say("full batch", name, T, total, nd)
+    bb = pkg.BatchBuilder(T, total, 1024, device=DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    od, dd_ = dev_u64(off), dev_u64(doff)
+    rows = bb.build_rows(wd, od)
+    del wd
+    out = torch.empty(nd, dtype=torch.int32, device=DEV)
+    seed = inputs.SAMPLE_SEED
+    out, sst = pkg.sample_batched_rows(rows, od, dd_, seed, out)
+    torch.cuda.synchronize()
+    assert (bb.status == 0).all()
+    assert int(sst.item()) == 0
+    rng = np.random.default_rng(1)
+    picks = sorted(set(rng.integers(0, T, size=6).tolist()) | {0, T - 1,
+                   int(np.argmax(np.diff(off.astype(np.int64))))})
+    for t in picks:
+        s, e = int(off[t]), int(off[t + 1])
+        ds, de = int(doff[t]), int(doff[t + 1])
+        pr, al = pkg.rows_split(rows[s:e])
+        p = pr.cpu().numpy()
+        a = al.cpu().numpy().view(np.uint32)
+        op, oa = oracle.psa_build(w[s:e], chunk=1024)
+        assert np.array_equal(a, oa), t
+        assert ulp_diff(p, op).max() <= 2, t
+        r = oracle.check(w[s:e], p, a)
+        assert r["max_rel"] <= 1e-12 and r["zero_violations"] == 0, (t, r)
+        k = min(de - ds, 200_000)
+        ref = oracle.sample(p, a, k, seed, first=0, table=t)
+        assert np.array_equal(out[ds:ds + k].cpu().numpy().view(np.uint32), ref), t
