@@ -57,6 +57,13 @@ def lib():
         L.oracle_philox4x32_10.restype = None
         L.oracle_sample.argtypes = [_ptr, _ptr, _u64, _u64, _u64, _u64, _u32, _ptr]
         L.oracle_sample.restype = None
+        L.oracle_sample_sectioned.argtypes = [_ptr, _ptr, _u64, _u64, _u64, _u32, _u32, _ptr,
+                                              _ptr]
+        L.oracle_sample_sectioned.restype = C.c_int
+        L.oracle_sectioned_counts.argtypes = [_u64, _u64, _u64, _u32, _u32, _ptr]
+        L.oracle_sectioned_counts.restype = C.c_int
+        L.oracle_sectioned_draw.argtypes = [_ptr, _ptr, _u64, _u64, _u32, _u32, _u64, _u64]
+        L.oracle_sectioned_draw.restype = C.c_uint32
         L.oracle_mass.argtypes = [_ptr, _ptr, _u64, _ptr, _ptr]
         L.oracle_mass.restype = C.c_int
         L.oracle_check.argtypes = [_ptr, _u64, _ptr, _ptr, _ptr, _ptr]
@@ -186,6 +193,36 @@ def sample(prob, alias, count, seed, first=0, table=0):
     lib().oracle_sample(_p(prob), _p(alias), prob.size, int(count), int(seed), int(first),
                         int(table), _p(out))
     return out
+
+
+def sample_sectioned(prob, alias, count, seed, log2r, table=0):
+    """Sectioned sampling: (out, counts per section); see the C source."""
+    prob = _f64(prob)
+    alias = np.ascontiguousarray(alias, dtype=np.uint32)
+    R = 1 << int(log2r)
+    S = (prob.size + R - 1) // R
+    out = np.empty(int(count), np.uint32)
+    counts = np.empty(S, np.uint64)
+    _raise(lib().oracle_sample_sectioned(_p(prob), _p(alias), prob.size, int(count), int(seed),
+                                         int(table), int(log2r), _p(out), _p(counts)),
+           "sample_sectioned")
+    return out, counts
+
+
+def sectioned_counts(n, count, seed, log2r, table=0):
+    R = 1 << int(log2r)
+    counts = np.empty((int(n) + R - 1) // R, np.uint64)
+    _raise(lib().oracle_sectioned_counts(int(n), int(count), int(seed), int(table), int(log2r),
+                                         _p(counts)), "sectioned_counts")
+    return counts
+
+
+def sectioned_draw(prob, alias, seed, log2r, sec, j, table=0):
+    """One draw of the sectioned sampler: draw j of section sec."""
+    prob = _f64(prob)
+    alias = np.ascontiguousarray(alias, dtype=np.uint32)
+    return int(lib().oracle_sectioned_draw(_p(prob), _p(alias), prob.size, int(seed), int(table),
+                                           int(log2r), int(sec), int(j)))
 
 
 def mass(prob, alias):

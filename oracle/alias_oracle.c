@@ -533,6 +533,85 @@ void oracle_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64
   }
 }
 
+/* Sectioned sampling (Sec. 5: the sectioned methods, which let a group of
+ * threads draw many samples from one cached section of the table), with the
+ * per-section sample counts drawn exactly instead of by the normal
+ * approximation the paper uses.  Rows are grouped into S = ceil(n / R)
+ * sections of R = 2^log2r rows (the last one may be shorter).
+ *   1. Counts.  `count` virtual draws v, two per Philox block: block b with
+ *      counter (b mod 2^32, b div 2^32, table, 1) gives virtual draws 2b
+ *      (words r0, r1) and 2b+1 (words r2, r3); the 64-bit word x of a virtual
+ *      draw picks row floor(x * n / 2^64), as a plain draw does, and c_s is
+ *      the number of virtual draws whose row lies in section s.  So
+ *      (c_0, ..., c_{S-1}) is multinomial with the sections' row shares.
+ *   2. Draws.  Section s's draws j = 0 .. c_s - 1 fill out[C_s + j], where
+ *      C_s = c_0 + ... + c_{s-1}: Philox block with counter (j mod 2^32,
+ *      j div 2^32, table, 2 + 4 s), row = s R + floor(x * R_s / 2^64) for the
+ *      first 64-bit word x and R_s rows in the section, coin from the last
+ *      two words exactly as a plain draw, out = row or alias[row].
+ * The output holds `count` independent draws from the table, grouped by
+ * section.  counts (may be NULL) receives c_s as uint64[S].  Returns 0, or
+ * -1 for invalid arguments (n == 0, log2r > 31, S > 2^26). */
+/* Step 1 alone: counts[s] for s < ceil(n / 2^log2r). */
+int oracle_sectioned_counts(uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
+                            uint32_t log2r, uint64_t *counts) {
+  if (n == 0 || log2r > 31) return -1;
+  const uint64_t R = 1ull << log2r;
+  const uint64_t S = (n + R - 1) / R;
+  if (S > (1ull << 26)) return -1;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (uint64_t sec = 0; sec < S; ++sec) counts[sec] = 0;
+  for (uint64_t v = 0; v < count; v += 2) {
+    const uint64_t b = v / 2;
+    uint32_t ctr[4] = {(uint32_t)b, (uint32_t)(b >> 32), table, 1u};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    for (int h = 0; h < 2 && v + (uint64_t)h < count; ++h) {
+      uint64_t x = (uint64_t)r[2 * h] | ((uint64_t)r[2 * h + 1] << 32);
+      uint64_t k = (uint64_t)(((unsigned __int128)x * n) >> 64);
+      counts[k / R] += 1;
+    }
+  }
+  return 0;
+}
+
+/* Step 2 for one draw: draw j of section sec. */
+uint32_t oracle_sectioned_draw(const double *prob, const uint32_t *alias, uint64_t n,
+                               uint64_t seed, uint32_t table, uint32_t log2r, uint64_t sec,
+                               uint64_t j) {
+  const uint64_t R = 1ull << log2r;
+  const uint64_t base = sec * R;
+  const uint64_t Rs = (n - base < R) ? n - base : R;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), table, 2u + 4u * (uint32_t)sec};
+  uint32_t r[4];
+  oracle_philox4x32_10(ctr, key, r);
+  uint64_t x = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
+  uint64_t k = base + (uint64_t)(((unsigned __int128)x * Rs) >> 64);
+  uint64_t u = ((uint64_t)r[2] | ((uint64_t)r[3] << 32)) >> 11;
+  return ((double)u * 0x1p-53 < prob[k]) ? (uint32_t)k : alias[k];
+}
+
+int oracle_sample_sectioned(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
+                            uint64_t seed, uint32_t table, uint32_t log2r, uint32_t *out,
+                            uint64_t *counts) {
+  if (n == 0 || log2r > 31) return -1;
+  const uint64_t R = 1ull << log2r;
+  const uint64_t S = (n + R - 1) / R;
+  if (S > (1ull << 26)) return -1;
+  uint64_t *c = (uint64_t *)calloc(S, sizeof(uint64_t));
+  if (!c) return -5;
+  oracle_sectioned_counts(n, count, seed, table, log2r, c);
+  uint64_t at = 0;
+  for (uint64_t sec = 0; sec < S; ++sec) {
+    for (uint64_t jj = 0; jj < c[sec]; ++jj)
+      out[at++] = oracle_sectioned_draw(prob, alias, n, seed, table, log2r, sec, jj);
+    if (counts) counts[sec] = c[sec];
+  }
+  free(c);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Checker (Sec. 2.2: each row is a bucket of W/N; row k gives prob[k] of a */
 /* bucket to item k and the rest to alias[k]).  Per-item reconstructed mass */

@@ -118,3 +118,33 @@ def sampler_distribution(prob, alias):
         out[k] += p_row * p_keep
         out[alias[k]] += p_row * (1 - p_keep)
     return out
+
+
+def sectioned_distribution(prob, alias, log2r):
+    """Exact law of one draw of the sectioned sampler: the section is that of
+    row floor(x*n/2^64), the row inside section s is s*R + floor(x'*R_s/2^64)
+    for an independent uniform 64-bit x', then the coin as in
+    sampler_distribution."""
+    n = len(prob)
+    R = 1 << log2r
+    two64 = 1 << 64
+
+    def ceil_div(a, b):
+        return -((-a) // b)
+
+    def xs_below(m, size):  # number of x in [0, 2^64) with floor(x*size/2^64) < m
+        return ceil_div(m * two64, size)
+
+    out = [Fraction(0)] * n
+    for base in range(0, n, R):
+        Rs = min(R, n - base)
+        p_sec = Fraction(xs_below(base + Rs, n) - xs_below(base, n), two64)
+        for k in range(base, base + Rs):
+            r = k - base
+            p_row = Fraction(xs_below(r + 1, Rs) - xs_below(r, Rs), two64)
+            thr = _fr(prob[k]) * (1 << 53)
+            keep = min(max(ceil_div(thr.numerator, thr.denominator), 0), 1 << 53)
+            p_keep = Fraction(keep, 1 << 53)
+            out[k] += p_sec * p_row * p_keep
+            out[alias[k]] += p_sec * p_row * (1 - p_keep)
+    return out

@@ -355,3 +355,70 @@ def test_sampler_first_draw_offset_is_a_window(oracle):
     assert np.array_equal(a[2000:3000], b)
     c = oracle.sample(prob, alias, 1000, 99, first=2000, table=1)
     assert not np.array_equal(b, c)
+
+
+# --------------------------------------------------------------------------
+# Sectioned sampling (Sec. 5 sectioned methods, exact section counts)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,log2r", [(23, 2), (17, 4), (9, 5)])
+def test_sectioned_exact_law_matches_masses(oracle, n, log2r):
+    w = inputs.lognormal(n, 1.0, n)
+    prob, alias = oracle.psa_build(w)
+    dist = exact.sectioned_distribution(prob.tolist(), alias.tolist(), log2r)
+    fr_w = [Fraction(float(x)) for x in w]
+    W = sum(fr_w)
+    bound = Fraction(1, 2**53) + Fraction(n + (1 << log2r), 2**64) + Fraction(1, 10**14)
+    for i in range(n):
+        assert abs(dist[i] - fr_w[i] / W) <= bound
+
+
+def test_sectioned_counts_follow_the_virtual_draws(oracle):
+    """c_s counts the virtual draws whose row lies in section s; the virtual
+    draws are the two 64-bit halves of Philox blocks (b, b>>32, table, 1)."""
+    n, log2r, count, seed, table = 1000, 6, 777, 4242, 3
+    w = inputs.uniform01(n, 5)
+    prob, alias = oracle.psa_build(w)
+    out, counts = oracle.sample_sectioned(prob, alias, count, seed, log2r, table=table)
+    ref = np.zeros(len(counts), np.uint64)
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+    for v in range(count):
+        r = oracle.philox(np.array([v // 2, 0, table, 1], np.uint32), key)
+        x = int(r[2 * (v % 2)]) | (int(r[2 * (v % 2) + 1]) << 32)
+        ref[((x * n) >> 64) >> log2r] += 1
+    assert np.array_equal(counts, ref)
+    assert int(counts.sum()) == count
+
+
+def test_sectioned_groups_hold_their_sections_rows(oracle):
+    n, log2r = 5000, 8
+    w = inputs.power_law(n, 1.0, 2)
+    prob, alias = oracle.psa_build(w, chunk=256)
+    out, counts = oracle.sample_sectioned(prob, alias, 200_000, 7, log2r)
+    R = 1 << log2r
+    at = 0
+    for s, c in enumerate(counts.tolist()):
+        rows = np.arange(s * R, min(n, (s + 1) * R))
+        allowed = np.union1d(rows, alias[rows])
+        assert np.isin(out[at:at + c], allowed).all()
+        at += c
+
+
+def test_sectioned_chi_squared_and_counts(oracle):
+    n, log2r = 5000, 7
+    w = inputs.power_law(n, 1.0, 8)
+    prob, alias = oracle.psa_build(w, chunk=1024)
+    draws = 2_000_000
+    out, counts = oracle.sample_sectioned(prob, alias, draws, inputs.SAMPLE_SEED, log2r)
+    hist = np.bincount(out, minlength=n)
+    stat, dof, p = oracle.chi2_gof(hist, draws * w / w.sum())
+    assert p >= 1e-3, (stat, dof, p)
+    R = 1 << log2r
+    share = np.array([min(R, n - s) for s in range(0, n, R)], np.float64) / n
+    stat, dof, p = oracle.chi2_gof(counts.astype(np.float64), draws * share)
+    assert p >= 1e-3, (stat, dof, p)
+
+
+def test_sectioned_rejects_bad_arguments(oracle):
+    prob, alias = oracle.psa_build(np.ones(10))
+    with pytest.raises(oracle.OracleError):
+        oracle.sample_sectioned(prob, alias, 10, 1, 40)
