@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-binary split comparison")
+    ap.add_argument("--no-sectioned", action="store_true",
+                    help="skip the sectioned-sampling measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-table workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--cpu-n", type=int, default=None,
@@ -165,6 +169,122 @@ def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
         }
         del b, bl
         torch.cuda.empty_cache()
+    return out
+
+
+def batched(pkg, inputs, name, per_table_loop=False, learned=False, reps=5, epochs=300):
+    """A batched workload: tuned launch shape, then build + sample of all
+    tables as one captured HIP graph (replay time), the build and the sample
+    launches timed separately, and optionally the per-table loop through the
+    single-table entry point and per-table learned splits."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    from paper_2106_12270_amd import tune
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w_h, off_h, doff_h = inputs.make_batch(name)
+    sizes = np.diff(off_h.astype(np.int64))
+    T, total, nd = len(sizes), len(w_h), int(doff_h[-1])
+    w = torch.from_numpy(w_h).to(dev)
+    del w_h
+    od = torch.from_numpy(off_h.view(np.int64)).to(dev)
+    dd_ = torch.from_numpy(doff_h.view(np.int64)).to(dev)
+    tuned = tune.tune(w, od, int(sizes.min()), int(sizes.max()), reps=3)
+    out = {"workload": name, "tables": T, "items": total, "draws": nd,
+           "tuned": {"chunk": tuned["chunk"], "pack_waves": tuned["pack_waves"],
+                     "cached": tuned["cached"], "candidates_ms": tuned["times"]}}
+
+    def timed(fn, k):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(k):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / k
+
+    rows = torch.empty((total, 4), dtype=torch.int32, device=dev)
+    res = torch.empty(nd, dtype=torch.int32, device=dev)
+    sst = torch.zeros(1, dtype=torch.int32, device=dev)
+    models = None
+    if learned:
+        b0 = pkg.BatchBuilder(T, total, tuned["chunk"], pack_waves=tuned["pack_waves"], device=dev)
+        b0.build_rows(w, od, rows=rows)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        models, loss = b0.fit_split_models(od, epochs=epochs)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out["learned_fit_ms"] = round(ev[0].elapsed_time(ev[1]), 3)
+        out["learned_model"] = "mlp 1-32-32-1 per table, fp32, %d epochs" % epochs
+        out["learned_max_loss"] = float(loss.max().item())
+        out["build_ms_binary"] = round(timed(lambda: b0.build_rows(w, od, rows=rows), reps), 4)
+        del b0
+        bb = pkg.BatchBuilder(T, total, tuned["chunk"], split="learned", model=models,
+                              model_stride=pkg.BatchBuilder.MODEL_STRIDE,
+                              pack_waves=tuned["pack_waves"], device=dev)
+    else:
+        bb = pkg.BatchBuilder(T, total, tuned["chunk"], pack_waves=tuned["pack_waves"],
+                              device=dev)
+
+    def step():
+        bb.build_rows(w, od, rows=rows)
+        pkg.sample_batched_rows(rows, od, dd_, inputs.SAMPLE_SEED, res, status=sst)
+
+    step()
+    torch.cuda.synchronize()
+    if int((bb.status != 0).sum().item()) or int(sst.item()):
+        raise SystemExit(f"{name}: batched build or sample failed")
+    if learned:
+        out["fallbacks"] = int(sum(h.split_fallbacks for h in bb.headers()))
+    out["build_ms"] = round(timed(lambda: bb.build_rows(w, od, rows=rows), reps), 4)
+    out["sample_ms"] = round(timed(lambda: pkg.sample_batched_rows(
+        rows, od, dd_, inputs.SAMPLE_SEED, res, status=sst), reps), 4)
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(stream)
+    with torch.cuda.stream(s2):
+        step()
+    stream.wait_stream(s2)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    out["graph_ms"] = round(timed(g.replay, reps), 4)
+    out["build_items_per_s"] = total / (out["build_ms"] * 1e-3)
+    out["build_hbm_frac"] = round(total * BUILD_BYTES_PER_ITEM / (out["build_ms"] * 1e-3)
+                                  / (HBM_PEAK_GBS * 1e9), 4)
+    out["samples_per_s"] = nd / (out["sample_ms"] * 1e-3)
+    if per_table_loop:
+        # the plain path: one single-table alias_build_rows per table, one stream
+        L = pkg.lib()
+        o = pkg.BuildOpts()
+        o.chunk_items = tuned["chunk"]
+        wsb = L.alias_build_workspace_bytes(int(sizes.max()), C.byref(o))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        stt = torch.zeros(T, dtype=torch.int32, device=dev)
+        sp = C.c_void_p(stream.cuda_stream)
+        wp, rp, tp_, wsp = w.data_ptr(), rows.data_ptr(), stt.data_ptr(), ws.data_ptr()
+        offl = off_h.astype(np.int64).tolist()
+
+        def loop():
+            for t in range(T):
+                a, b = offl[t], offl[t + 1]
+                r = L.alias_build_rows(C.c_void_p(wp + 8 * a), b - a, C.c_void_p(rp + 16 * a),
+                                       C.c_void_p(wsp), wsb, C.c_void_p(tp_ + 4 * t),
+                                       C.byref(o), sp)
+                if r:
+                    raise SystemExit(f"alias_build_rows failed for table {t}")
+
+        out["per_table_loop_build_ms"] = round(timed(loop, 1), 3)
+        out["batched_speedup_vs_loop"] = round(out["per_table_loop_build_ms"] / out["build_ms"], 2)
+    del bb, rows, res, w
+    torch.cuda.empty_cache()
     return out
 
 
@@ -310,11 +430,43 @@ def main():
         "samples_per_s": draws / (s_ms * 1e-3),
         "roofline": roof,
     }
+    # sectioned sampling (draws grouped by table section, Sec. 5) from the
+    # same table: the 10^9 draws again, timed on the same stream
+    if rows_layout and not args.no_sectioned:
+        sec = {}
+        for log2r in (14, 16, 18):
+            ss = pkg.SectionedSampler(n, draws, log2r, device=dev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, out=out, stream=stream)
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for _ in range(3):
+                ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, out=out, stream=stream)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 3
+            sec[f"log2r_{log2r}"] = {"ms": round(ms, 3), "samples_per_s": draws / (ms * 1e-3)}
+            del ss
+        best = min(sec.values(), key=lambda v: v["ms"])
+        result["sectioned_sampling"] = {
+            "draws": draws, "by_section_rows": sec, "best_ms": best["ms"],
+            "best_samples_per_s": best["samples_per_s"],
+            "speedup_vs_plain": round(s_ms / best["ms"], 2),
+            "note": "same table and draw count; draws grouped by section of 2^log2r rows "
+                    "with exact per-section counts"}
+    del w, out, builder, prob, alias
+    if rows_layout:
+        del rows
+    torch.cuda.empty_cache()
     if not args.no_learned:
         print("[bench] learned vs binary split", file=sys.stderr, flush=True)
-        del w, out
-        torch.cuda.empty_cache()
         result["learned_vs_binary"] = learned_vs_binary(pkg, inputs)
+    if not args.no_batched:
+        for bname, loop, lrn in (("batch_100k_16_65536", True, False),
+                                 ("batch_1024_2p14_2p22", True, True)):
+            print(f"[bench] batched {bname}", file=sys.stderr, flush=True)
+            result.setdefault("batched", []).append(
+                batched(pkg, inputs, bname, per_table_loop=loop, learned=lrn))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_n, args.cpu_draws)

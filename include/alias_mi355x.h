@@ -68,8 +68,10 @@ typedef struct alias_build_opts {
                                   model whose declared parameters do not fit */
   uint64_t split_model_stride; /* batched builds: bytes from one table's model
                                   to the next; 0 = all tables share one model */
-  uint32_t pack_waves;     /* sections packed per block, 1..4; 0 = as many as
-                              the LDS allows (an autotuning knob) */
+  uint32_t pack_waves;     /* waves that pack one section together: 1, 2 or 4,
+                              with chunk_items / (64 * pack_waves) rows per
+                              thread in {1, 2, 4, 8}; 0 = min(4, chunk/64)
+                              (an autotuning knob) */
   uint32_t reserved;       /* must be zero */
 } alias_build_opts;
 
@@ -170,6 +172,49 @@ int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t s
                       uint64_t first_draw, uint32_t table_id, uint32_t *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Sectioned sampling (Sec. 5, the sectioned methods: a group of threads
+ * serves many draws from one section of the table held in cache).  The
+ * rows are grouped into S = ceil(n / R) sections of R = 2^log2r rows (the
+ * last may be shorter) and the draws are produced section by section, so
+ * the gathers of a section hit a range of R rows that stays in the L2 cache
+ * instead of one random HBM line per draw.  The number of draws per section
+ * is drawn exactly (the paper uses a normal approximation):
+ *   1. count virtual draws v, two per Philox4x32-10 block b with counter
+ *      (b mod 2^32, b div 2^32, table_id, 1), key as in alias_sample:
+ *      virtual draw 2b takes the 64-bit word r0 + 2^32 r1, draw 2b+1 the word
+ *      r2 + 2^32 r3; each picks row floor(x * n / 2^64) exactly as a plain
+ *      draw, and c_s is the number of virtual draws in section s;
+ *   2. section s's draws j = 0 .. c_s - 1 are written to out[C_s + j],
+ *      C_s = c_0 + ... + c_{s-1}: Philox block with counter
+ *      (j mod 2^32, j div 2^32, table_id, 2 + 4 s), row = s R +
+ *      floor(x * R_s / 2^64) with R_s the rows of section s, coin and output
+ *      exactly as alias_sample.
+ * The output holds `count` independent draws from the table grouped by
+ * section (not in the order of alias_sample's stream), bit-reproducible
+ * from (table, count, seed, table_id, log2r).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes (0 if invalid: n not in [1, 2^32 - 1], log2r not in
+ * [6, 31], more than 2^20 sections, or count > 2^40). */
+size_t alias_sample_sectioned_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r);
+
+/* Sectioned sampling from a two-array table.
+ *   d_out     device, count uint32 (grouped by section, see above)
+ *   d_counts  device uint64[S] receiving c_s, or NULL
+ *   d_ws      device workspace of alias_sample_sectioned_workspace_bytes()
+ *             bytes, 256-byte aligned
+ * Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE or ALIAS_EHIP. */
+int alias_sample_sectioned(const double *d_prob, const uint32_t *d_alias, uint64_t n,
+                           uint64_t count, uint64_t seed, uint32_t table_id, uint32_t log2r,
+                           uint32_t *d_out, uint64_t *d_counts, void *d_ws, size_t ws_bytes,
+                           void *stream);
+
+/* The same draws from a table of 16-byte rows. */
+int alias_sample_sectioned_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
+                                uint32_t table_id, uint32_t log2r, uint32_t *d_out,
+                                uint64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched tables (an added system pattern: many independent distributions,
  * e.g. one per graph vertex or per topic, the motivation of Sec. 1).  T
  * tables of uneven sizes are stored back to back: table t owns items
@@ -242,6 +287,36 @@ int alias_sample_batched_rows(const void *d_rows, const uint64_t *d_offsets, uin
                               int32_t *d_status, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Autotuning (an added system pattern): the rows per section (chunk_items)
+ * and the waves that pack one section (pack_waves) are timed on the device
+ * for a given batch and the fastest pair is returned.  Tables built with
+ * different options may differ in the last bit of a probability (the
+ * arithmetic is regrouped), never in an alias or in the mass invariant; the
+ * options chosen are returned so that later builds can reuse them.
+ * ------------------------------------------------------------------------ */
+
+/* Largest workspace of a batched build over the candidate chunk sizes (0 if
+ * none is valid). */
+size_t alias_tune_workspace_bytes(uint32_t T, uint64_t total_items, const alias_build_opts *base,
+                                  const uint32_t *chunks, uint32_t n_chunks);
+
+/* Time alias_build_batched_rows for every valid (chunks[c], waves[v]) pair,
+ * other options from *base (NULL: defaults): one untimed build, then `reps`
+ * builds between two HIP events on `stream`.  times_ms (host, n_chunks *
+ * n_waves floats, row-major by chunk) receives the mean time per build or -1
+ * for a pair that is not valid; *best (host) the options of the fastest.
+ * d_rows, d_ws, d_status: as for alias_build_batched_rows, the workspace of
+ * alias_tune_workspace_bytes() bytes.  Unlike the build entry points this
+ * call synchronises with the stream (it waits for its timing events), so it
+ * cannot be captured in a graph.  Returns ALIAS_OK, ALIAS_EINVAL (also when
+ * no pair is valid) or ALIAS_EHIP. */
+int alias_tune_build(const double *d_w, const uint64_t *d_offsets, uint32_t T, uint64_t total_items,
+                     void *d_rows, void *d_ws, size_t ws_bytes, int32_t *d_status,
+                     const alias_build_opts *base, const uint32_t *chunks, uint32_t n_chunks,
+                     const uint32_t *waves, uint32_t n_waves, uint32_t reps, float *times_ms,
+                     alias_build_opts *best, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned split predictor (an added system pattern; the paper's splits use
  * binary search, Sec. 4.1).  A small model maps a section boundary x = m/n
  * to y = j/H, the fraction of heavy items closed after m rows; the split
@@ -290,6 +365,36 @@ int alias_split_model_grad(uint32_t kind, uint32_t segments, const void *d_model
                            size_t model_bytes, const float *d_x, const float *d_t, uint64_t points,
                            double *d_grad, double *d_loss, void *d_train_ws,
                            size_t train_ws_bytes, void *stream);
+
+/* Workspace bytes of alias_split_model_fit_batched for a batched build of T
+ * tables and total_items items with build_opts (0 if invalid; kind must be
+ * ALIAS_MODEL_MLP). */
+size_t alias_split_model_fit_batched_workspace_bytes(uint32_t T, uint64_t total_items,
+                                                     const alias_build_opts *build_opts,
+                                                     uint32_t kind);
+
+/* Train one MLP split model per table of a finished batched build, on the
+ * GPU, one workgroup per table for all epochs in a single launch.  Table t's
+ * training boundaries, loss, optimiser and step sizes are those of
+ * alias_split_model_fit on that table alone, and its model is bit for bit
+ * the model that call would write.  A table whose build failed gets a model
+ * with eps = -1, which the split kernel never trusts, and a NaN loss.
+ *   d_build_ws, d_offsets, T, total_items, build_opts  the finished batched
+ *               build (workspace, offsets and options it was built with)
+ *   kind        ALIAS_MODEL_MLP (the only kind trained in batches)
+ *   d_models    device, T blobs, table t's at byte t * model_stride;
+ *               model_stride >= alias_split_model_bytes(ALIAS_MODEL_MLP, 0),
+ *               a multiple of 4.  Pass the same pointer and stride to a
+ *               batched learned build (split_model, split_model_stride).
+ *   d_train_ws  device scratch of alias_split_model_fit_batched_workspace_bytes()
+ *               bytes, 256-byte aligned
+ *   d_loss      device, T doubles receiving each table's final loss, or NULL
+ * Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE or ALIAS_EHIP. */
+int alias_split_model_fit_batched(const void *d_build_ws, const uint64_t *d_offsets, uint32_t T,
+                                  uint64_t total_items, const alias_build_opts *build_opts,
+                                  uint32_t kind, uint32_t epochs, float lr, void *d_models,
+                                  size_t model_stride, void *d_train_ws, size_t train_ws_bytes,
+                                  double *d_loss, void *stream);
 
 /* Recompute the splits of a finished build in d_ws with the split method in
  * opts (binary, or learned with a model); the partition and prefix sums are

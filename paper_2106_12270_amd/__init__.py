@@ -12,7 +12,7 @@ import os
 __all__ = [
     "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
     "sample", "build_rows", "sample_rows", "rows_split", "Builder", "status_str",
-    "BatchBuilder", "sample_batched", "sample_batched_rows",
+    "BatchBuilder", "sample_batched", "sample_batched_rows", "SectionedSampler",
     "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
     "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
 ]
@@ -112,6 +112,21 @@ def lib():
         L.alias_sample_batched.restype = C.c_int
         L.alias_sample_batched_rows.argtypes = [vp, vp, u32, u64, vp, u64, u64, vp, vp, vp]
         L.alias_sample_batched_rows.restype = C.c_int
+        L.alias_split_model_fit_batched_workspace_bytes.argtypes = [u32, u64,
+                                                                    C.POINTER(BuildOpts), u32]
+        L.alias_split_model_fit_batched_workspace_bytes.restype = C.c_size_t
+        L.alias_split_model_fit_batched.argtypes = [vp, vp, u32, u64, C.POINTER(BuildOpts), u32,
+                                                    u32, C.c_float, vp, C.c_size_t, vp,
+                                                    C.c_size_t, vp, vp]
+        L.alias_split_model_fit_batched.restype = C.c_int
+        L.alias_sample_sectioned_workspace_bytes.argtypes = [u64, u64, u32]
+        L.alias_sample_sectioned_workspace_bytes.restype = C.c_size_t
+        L.alias_sample_sectioned.argtypes = [vp, vp, u64, u64, u64, u32, u32, vp, vp, vp,
+                                             C.c_size_t, vp]
+        L.alias_sample_sectioned.restype = C.c_int
+        L.alias_sample_sectioned_rows.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp,
+                                                  C.c_size_t, vp]
+        L.alias_sample_sectioned_rows.restype = C.c_int
         L.alias_status_str.argtypes = [C.c_int]
         L.alias_status_str.restype = C.c_char_p
         L.alias_version.argtypes = []
@@ -499,6 +514,33 @@ class BatchBuilder:
             raise AliasError(st, "alias_build_batched_rows")
         return rows
 
+    MODEL_STRIDE = 4640  # one MLP blob (4628 bytes) rounded up to 16
+
+    def fit_split_models(self, offsets, epochs=300, lr=0.02, stream=None):
+        """Train one MLP split model per table on the splits of the last
+        build (binary split).  Returns (models uint8 tensor of T blobs at
+        MODEL_STRIDE bytes apart, per-table final loss float64 tensor)."""
+        import torch
+
+        _check_dev(offsets, torch.int64, "offsets")
+        o = _opts(self.chunk, "binary", pack_waves=self.opts.pack_waves)
+        tb = lib().alias_split_model_fit_batched_workspace_bytes(self.T, self.total, C.byref(o),
+                                                                 MODEL_MLP)
+        if tb == 0:
+            raise AliasError(ALIAS_EINVAL, "alias_split_model_fit_batched_workspace_bytes")
+        dev = self.ws.device
+        models = torch.zeros(self.T * self.MODEL_STRIDE, dtype=torch.uint8, device=dev)
+        tws = torch.empty(tb, dtype=torch.uint8, device=dev)
+        loss = torch.zeros(self.T, dtype=torch.float64, device=dev)
+        st = lib().alias_split_model_fit_batched(_ptr(self.ws), _ptr(offsets), self.T, self.total,
+                                                 C.byref(o), MODEL_MLP, int(epochs), float(lr),
+                                                 _ptr(models), self.MODEL_STRIDE, _ptr(tws), tb,
+                                                 _ptr(loss), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_split_model_fit_batched")
+        self._train_ws = tws
+        return models, loss
+
     def headers(self):
         """Per-table workspace headers of the last build (synchronises)."""
         sz = C.sizeof(WsHeader)
@@ -552,3 +594,53 @@ def sample_batched_rows(rows, offsets, draw_offsets, seed, out, status=None, str
     if st:
         raise AliasError(st, "alias_sample_batched_rows")
     return out, status
+
+
+# ---------------------------------------------------------------------------
+# Sectioned sampling
+# ---------------------------------------------------------------------------
+class SectionedSampler:
+    """Owns the workspace of sectioned sampling for (n, count, log2r): the
+    draws grouped by table section of 2^log2r rows (see the C header)."""
+
+    def __init__(self, n, count, log2r, device="cuda"):
+        import torch
+
+        self.n, self.count, self.log2r = int(n), int(count), int(log2r)
+        b = lib().alias_sample_sectioned_workspace_bytes(self.n, self.count, self.log2r)
+        if b == 0:
+            raise AliasError(ALIAS_EINVAL, "alias_sample_sectioned_workspace_bytes")
+        self.ws_bytes = b
+        self.ws = torch.empty(b, dtype=torch.uint8, device=device)
+        self.sections = (self.n + (1 << self.log2r) - 1) >> self.log2r
+
+    def sample_rows(self, rows, seed, table_id=0, out=None, counts=None, stream=None):
+        import torch
+
+        _check_rows(rows, self.n)
+        if out is None:
+            out = torch.empty(self.count, dtype=torch.int32, device=rows.device)
+        _check_dev(out, torch.int32, "out")
+        st = lib().alias_sample_sectioned_rows(
+            _ptr(rows), self.n, self.count, int(seed) & (2**64 - 1), int(table_id), self.log2r,
+            _ptr(out), _ptr(counts) if counts is not None else None, _ptr(self.ws),
+            self.ws_bytes, _stream(stream))
+        if st:
+            raise AliasError(st, "alias_sample_sectioned_rows")
+        return out
+
+    def sample(self, prob, alias, seed, table_id=0, out=None, counts=None, stream=None):
+        import torch
+
+        _check_dev(prob, torch.float64, "prob")
+        _check_dev(alias, torch.int32, "alias")
+        if out is None:
+            out = torch.empty(self.count, dtype=torch.int32, device=prob.device)
+        _check_dev(out, torch.int32, "out")
+        st = lib().alias_sample_sectioned(
+            _ptr(prob), _ptr(alias), self.n, self.count, int(seed) & (2**64 - 1), int(table_id),
+            self.log2r, _ptr(out), _ptr(counts) if counts is not None else None, _ptr(self.ws),
+            self.ws_bytes, _stream(stream))
+        if st:
+            raise AliasError(st, "alias_sample_sectioned")
+        return out

@@ -20,6 +20,11 @@ int launch_sample_batched(const double *prob, const uint32_t *alias, const Table
                           const uint64_t *offsets, const uint64_t *draw_off, uint32_t T,
                           uint64_t total_items, uint64_t total_draws, uint64_t seed,
                           uint32_t *out, int32_t *status, hipStream_t st);
+size_t sec_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r);
+int launch_sample_sectioned(const double *prob, const uint32_t *alias, const TableRow *rows,
+                            uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
+                            uint32_t log2r, uint32_t *out, uint64_t *d_counts, void *d_ws,
+                            size_t ws_bytes, hipStream_t st);
 int launch_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64_t count,
                   uint64_t seed, uint64_t first, uint32_t table, uint32_t *out, hipStream_t st);
 int launch_sample_rows(const TableRow *rows, uint64_t n, uint64_t count, uint64_t seed,
@@ -212,6 +217,122 @@ int alias_sample_batched_rows(const void *d_rows, const uint64_t *d_offsets, uin
   return launch_sample_batched(nullptr, nullptr, (const TableRow *)d_rows, d_offsets,
                                d_draw_offsets, T, total_items, total_draws, seed, d_out, d_status,
                                (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Sectioned sampling
+// ---------------------------------------------------------------------------
+size_t alias_sample_sectioned_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r) {
+  return sec_workspace_bytes(n, count, log2r);
+}
+
+static int sectioned_common(uint64_t n, uint64_t count, uint32_t log2r, const uint32_t *d_out,
+                            const uint64_t *d_counts, const void *d_ws) {
+  if (sec_workspace_bytes(n, count, log2r) == 0) return ALIAS_EINVAL;
+  if ((count && !d_out) || !d_ws || !aligned(d_out, 4) || !aligned(d_ws, 256)) return ALIAS_EINVAL;
+  if (d_counts && !aligned(d_counts, 8)) return ALIAS_EINVAL;
+  return ALIAS_OK;
+}
+
+int alias_sample_sectioned(const double *d_prob, const uint32_t *d_alias, uint64_t n,
+                           uint64_t count, uint64_t seed, uint32_t table_id, uint32_t log2r,
+                           uint32_t *d_out, uint64_t *d_counts, void *d_ws, size_t ws_bytes,
+                           void *stream) {
+  if (!d_prob || !d_alias || !aligned(d_prob, 8) || !aligned(d_alias, 4)) return ALIAS_EINVAL;
+  const int st = sectioned_common(n, count, log2r, d_out, d_counts, d_ws);
+  if (st) return st;
+  return launch_sample_sectioned(d_prob, d_alias, nullptr, n, count, seed, table_id, log2r, d_out,
+                                 d_counts, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int alias_sample_sectioned_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t seed,
+                                uint32_t table_id, uint32_t log2r, uint32_t *d_out,
+                                uint64_t *d_counts, void *d_ws, size_t ws_bytes, void *stream) {
+  if (!d_rows || !aligned(d_rows, 16)) return ALIAS_EINVAL;
+  const int st = sectioned_common(n, count, log2r, d_out, d_counts, d_ws);
+  if (st) return st;
+  return launch_sample_sectioned(nullptr, nullptr, (const TableRow *)d_rows, n, count, seed,
+                                 table_id, log2r, d_out, d_counts, d_ws, ws_bytes,
+                                 (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the launch shape
+// ---------------------------------------------------------------------------
+size_t alias_tune_workspace_bytes(uint32_t T, uint64_t total_items, const alias_build_opts *base,
+                                  const uint32_t *chunks, uint32_t n_chunks) {
+  size_t best = 0;
+  if (!chunks || n_chunks == 0) return 0;
+  for (uint32_t c = 0; c < n_chunks; ++c) {
+    alias_build_opts o = base ? *base : alias_build_opts{};
+    o.chunk_items = chunks[c];
+    o.pack_waves = 0;
+    Layout L;
+    if (!compute_layout_batch(T, total_items, &o, &L)) continue;
+    if (L.pub.total_bytes > best) best = (size_t)L.pub.total_bytes;
+  }
+  return best;
+}
+
+int alias_tune_build(const double *d_w, const uint64_t *d_offsets, uint32_t T, uint64_t total_items,
+                     void *d_rows, void *d_ws, size_t ws_bytes, int32_t *d_status,
+                     const alias_build_opts *base, const uint32_t *chunks, uint32_t n_chunks,
+                     const uint32_t *waves, uint32_t n_waves, uint32_t reps, float *times_ms,
+                     alias_build_opts *best, void *stream) {
+  if (!chunks || !waves || n_chunks == 0 || n_waves == 0 || !times_ms || !best) return ALIAS_EINVAL;
+  if (reps == 0 || reps > 1000 || n_chunks > 64 || n_waves > 64) return ALIAS_EINVAL;
+  if (!d_rows || !aligned(d_rows, 16)) return ALIAS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return ALIAS_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ALIAS_EHIP;
+  }
+  int rc = ALIAS_OK;
+  float best_ms = -1.0f;
+  for (uint32_t c = 0; c < n_chunks && rc == ALIAS_OK; ++c) {
+    for (uint32_t v = 0; v < n_waves && rc == ALIAS_OK; ++v) {
+      float *slot = &times_ms[c * n_waves + v];
+      *slot = -1.0f;  // not a valid combination
+      alias_build_opts o = base ? *base : alias_build_opts{};
+      o.chunk_items = chunks[c];
+      o.pack_waves = waves[v];
+      Layout L;
+      const unsigned char *models;
+      uint64_t mb, ms;
+      if (batched_common(d_w, d_offsets, T, total_items, d_ws, ws_bytes, d_status, &o, &L,
+                         &models, &mb, &ms) != ALIAS_OK)
+        continue;
+      // one untimed build, then `reps` timed ones
+      int r = launch_build_batch(d_w, d_offsets, 0, nullptr, nullptr, (TableRow *)d_rows, d_ws,
+                                 d_status, L, models, mb, ms, st);
+      if (r == ALIAS_EINVAL) continue;  // the launch shape does not fit this device
+      if (r != ALIAS_OK || hipEventRecord(e0, st) != hipSuccess) {
+        rc = ALIAS_EHIP;
+        break;
+      }
+      for (uint32_t k = 0; k < reps && r == ALIAS_OK; ++k)
+        r = launch_build_batch(d_w, d_offsets, 0, nullptr, nullptr, (TableRow *)d_rows, d_ws,
+                               d_status, L, models, mb, ms, st);
+      float ms_total = 0.0f;
+      if (r != ALIAS_OK || hipEventRecord(e1, st) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms_total, e0, e1) != hipSuccess) {
+        rc = ALIAS_EHIP;
+        break;
+      }
+      *slot = ms_total / (float)reps;
+      if (best_ms < 0.0f || *slot < best_ms) {
+        best_ms = *slot;
+        *best = o;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == ALIAS_OK && best_ms < 0.0f) rc = ALIAS_EINVAL;  // no valid candidate
+  return rc;
 }
 
 const char *alias_status_str(int code) {

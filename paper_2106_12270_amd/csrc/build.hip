@@ -3,19 +3,22 @@
 // batch of T tables of any sizes given by CSR offsets.
 //
 // Pipeline, one stream, no host synchronisation or readback:
-//   k_setup_*        per table: number of 4096-item tiles and of C-row
-//                    sections, their prefix sums; table headers reset.
+//   k_setup_*        per table: number of 4096-item tiles, of C-row sections
+//                    and of 1024-tile groups, their prefix sums; headers reset.
 //   k_reduce_tile    per tile: double-double sum of the weights + validation.
+//   k_reduce_group   per tile group: sum of its tiles' sums.
 //   k_finalize       per table: W, W/N, status (fixed combination order).
 //   k_tilesum        per tile: light count, light and heavy weight sums.
-//   k_tilescan       per table: exclusive prefix of its tiles' sums.
+//   k_scan_group     per tile group: exclusive prefix of its tiles' sums.
+//   k_scan_table     per table: exclusive prefix of its groups' sums; L, H.
 //   k_partition      per tile: stable light/heavy partition in item order;
 //                    entries carry their weight (Sec. 4.2 "Weight in l and h
 //                    Arrays"); prefix sums emitted every 64 entries.
 //   k_split          per section boundary: lights used, heavies closed and
 //                    spill after m = k*C rows (Sec. 2.2; Sec. 4.1 binary
 //                    search baseline), or the learned variant.
-//   k_pack           one wave per section: the sweep of Sec. 4.2 in LDS.
+//   k_pack           one block per section: the sweep of Sec. 4.2 as a merge
+//                    of two sorted sequences, in LDS.
 // A tile, section or boundary finds its table by binary search over the
 // per-table prefix arrays.  Every sum is formed in a fixed order, so builds
 // are bit-reproducible.  Item ids stored in the light / heavy lists and in
@@ -39,11 +42,12 @@ struct Batch {
   alias_ws_header *hdr;      // T table headers
   uint64_t *tile_start;      // T+1
   uint64_t *sec_start;       // T+1
+  uint64_t *grp_start;       // T+1: tile groups of kScanTiles tiles
   uint32_t *flags;           // [0] != 0: inconsistent batch description
-  uint64_t *grp;             // setup scratch
-  ReducePart *tilew;
+  uint64_t *sscr;            // setup scratch
+  ReducePart *tilew, *grpw;
   TileSum *tsum;
-  TilePrefix *tpre;
+  TilePrefix *tpre, *gsum, *gpre;
   uint32_t *l_idx, *h_idx;   // table t's lists start at offsets[t]
   double *l_w, *h_w;
   dd *agg_l, *agg_h;         // table t's prefix points start at agg_base(t)
@@ -52,7 +56,7 @@ struct Batch {
   int32_t *status;           // T status words
   const unsigned char *models;  // learned split: model blobs (or nullptr)
   uint64_t model_bytes, model_stride;
-  uint64_t tiles_max, secs_max;
+  uint64_t tiles_max, secs_max, groups_max;
 };
 
 __device__ __forceinline__ void table_range(const Batch &B, uint32_t t, uint64_t &off,
@@ -71,42 +75,17 @@ __device__ __forceinline__ uint64_t agg_base(uint64_t off, uint32_t t) {
   return off / kAggStride + 2ull * t;
 }
 
-// largest t in [0, T) with start[t] <= x (start nondecreasing, start[T] > x)
-__device__ __forceinline__ uint32_t find_table(const uint64_t *start, uint32_t T, uint64_t x) {
-  uint32_t lo = 0, hi = T;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (start[mid] <= x)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// the same over boundary indices: table t's boundaries start at sec_start[t] + t
-__device__ __forceinline__ uint32_t find_table_bnd(const uint64_t *sec, uint32_t T, uint64_t x) {
-  uint32_t lo = 0, hi = T;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (sec[mid] + mid <= x)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // ---------------------------------------------------------------------------
 // Block reductions (fixed combination order)
 // ---------------------------------------------------------------------------
+// sum of nonnegative terms over the block (same-sign additions)
 __device__ __forceinline__ dd block_sum_dd(dd v, dd *s_wave /*[blockDim/64]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_sum(v);
+  v = wave_sum_fast(v);
   if (lane == 0) s_wave[wave] = v;
   __syncthreads();
   dd t = s_wave[0];
-  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = t + s_wave[k];
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = add_fast(t, s_wave[k]);
   __syncthreads();
   return t;
 }
@@ -127,14 +106,62 @@ __device__ __forceinline__ uint64_t wave_incl_u64(uint64_t v, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Setup: tiles and sections per table, their exclusive prefixes (two levels
-// of kSetupGroup tables), table headers reset.
+// Setup: tiles, sections and tile groups per table, their exclusive prefixes
+// (two levels of kSetupGroup tables), table headers reset.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSetupGroup) void k_setup_local(Batch B, bool single_group) {
-  __shared__ uint64_t s_t[kSetupGroup / 64], s_s[kSetupGroup / 64];
+struct Count3 {
+  uint64_t t, s, g;
+};
+
+__device__ __forceinline__ Count3 c3_add(Count3 a, Count3 b) {
+  a.t += b.t;
+  a.s += b.s;
+  a.g += b.g;
+  return a;
+}
+
+__device__ __forceinline__ Count3 wave_incl_c3(Count3 v, int lane) {
+  v.t = wave_incl_u64(v.t, lane);
+  v.s = wave_incl_u64(v.s, lane);
+  v.g = wave_incl_u64(v.g, lane);
+  return v;
+}
+
+// exclusive prefix of v over a kSetupGroup-thread block; *tot = block total
+__device__ __forceinline__ Count3 block_excl_c3(Count3 v, Count3 *s_w, Count3 *tot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const Count3 inc = wave_incl_c3(v, lane);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  Count3 o = {0, 0, 0}, tt = {0, 0, 0};
+  for (int k = 0; k < kSetupGroup / 64; ++k) {
+    if (k < wave) o = c3_add(o, s_w[k]);
+    tt = c3_add(tt, s_w[k]);
+  }
+  __syncthreads();
+  *tot = tt;
+  Count3 ex;
+  ex.t = o.t + inc.t - v.t;
+  ex.s = o.s + inc.s - v.s;
+  ex.g = o.g + inc.g - v.g;
+  return ex;
+}
+
+__device__ __forceinline__ void setup_check(const Batch &B, const Count3 &tot) {
+  const uint64_t last = B.offsets ? B.offsets[B.T] : B.n1;
+  const uint64_t first = B.offsets ? B.offsets[0] : 0;
+  B.tile_start[B.T] = tot.t;
+  B.sec_start[B.T] = tot.s;
+  B.grp_start[B.T] = tot.g;
+  if (first != 0 || last != B.total || tot.t > B.tiles_max || tot.s + B.T > B.secs_max ||
+      tot.g > B.groups_max)
+    atomicOr(&B.flags[0], 1u);
+}
+
+__global__ __launch_bounds__(kSetupGroup) void k_setup_local(Batch B, bool single_block) {
+  __shared__ Count3 s_w[kSetupGroup / 64];
   const uint32_t t = blockIdx.x * kSetupGroup + threadIdx.x;
-  uint64_t nt = 0, ns = 0;
+  Count3 c = {0, 0, 0};
   if (t < B.T) {
     uint64_t off, n;
     table_range(B, t, off, n);
@@ -142,8 +169,9 @@ __global__ __launch_bounds__(kSetupGroup) void k_setup_local(Batch B, bool singl
     if (!ok) atomicOr(&B.flags[0], 1u);
     const bool usable = ok && n >= 1 && n <= 0xFFFFFFFFull;
     if (usable) {
-      nt = (n + kTileItems - 1) / kTileItems;
-      ns = (n + B.chunk - 1) / B.chunk;
+      c.t = (n + kTileItems - 1) / kTileItems;
+      c.s = (n + B.chunk - 1) / B.chunk;
+      c.g = (c.t + kScanTiles - 1) / kScanTiles;
     }
     alias_ws_header h;
     h.W_hi = h.W_lo = h.avg_hi = h.avg_lo = 0.0;
@@ -156,79 +184,60 @@ __global__ __launch_bounds__(kSetupGroup) void k_setup_local(Batch B, bool singl
     B.hdr[t] = h;
     B.status[t] = h.status;
   }
-  const uint64_t it = wave_incl_u64(nt, lane), is = wave_incl_u64(ns, lane);
-  if (lane == 63) {
-    s_t[wave] = it;
-    s_s[wave] = is;
-  }
-  __syncthreads();
-  uint64_t ot = 0, os = 0, tt = 0, ts = 0;
-  for (int k = 0; k < kSetupGroup / 64; ++k) {
-    if (k < wave) {
-      ot += s_t[k];
-      os += s_s[k];
-    }
-    tt += s_t[k];
-    ts += s_s[k];
-  }
+  Count3 tot;
+  const Count3 ex = block_excl_c3(c, s_w, &tot);
   if (t < B.T) {
-    B.tile_start[t] = ot + it - nt;
-    B.sec_start[t] = os + is - ns;
+    B.tile_start[t] = ex.t;
+    B.sec_start[t] = ex.s;
+    B.grp_start[t] = ex.g;
   }
   if (threadIdx.x == 0) {
-    B.grp[2 * blockIdx.x] = tt;
-    B.grp[2 * blockIdx.x + 1] = ts;
-  }
-  if (single_group && threadIdx.x == 0) {
-    B.tile_start[B.T] = tt;
-    B.sec_start[B.T] = ts;
-    const uint64_t last = B.offsets ? B.offsets[B.T] : B.n1;
-    const uint64_t first = B.offsets ? B.offsets[0] : 0;
-    if (first != 0 || last != B.total || tt > B.tiles_max || ts + B.T > B.secs_max)
-      atomicOr(&B.flags[0], 1u);
+    B.sscr[3 * blockIdx.x] = tot.t;
+    B.sscr[3 * blockIdx.x + 1] = tot.s;
+    B.sscr[3 * blockIdx.x + 2] = tot.g;
+    if (single_block) setup_check(B, tot);
   }
 }
 
-// exclusive prefix over the groups; final entries; consistency checks
-__global__ __launch_bounds__(kSetupGroup) void k_setup_groups(Batch B, uint32_t groups) {
-  __shared__ uint64_t s_t[kSetupGroup / 64], s_s[kSetupGroup / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// exclusive prefix over the setup blocks (at most kSetupGroup of them:
+// T <= 2^20); final entries; consistency checks
+__global__ __launch_bounds__(kSetupGroup) void k_setup_groups(Batch B, uint32_t blocks) {
+  __shared__ Count3 s_w[kSetupGroup / 64];
   const uint32_t g = threadIdx.x;
-  const uint64_t nt = g < groups ? B.grp[2 * g] : 0, ns = g < groups ? B.grp[2 * g + 1] : 0;
-  const uint64_t it = wave_incl_u64(nt, lane), is = wave_incl_u64(ns, lane);
-  if (lane == 63) {
-    s_t[wave] = it;
-    s_s[wave] = is;
+  Count3 c = {0, 0, 0};
+  if (g < blocks) {
+    c.t = B.sscr[3 * g];
+    c.s = B.sscr[3 * g + 1];
+    c.g = B.sscr[3 * g + 2];
   }
-  __syncthreads();
-  uint64_t ot = 0, os = 0, tt = 0, ts = 0;
-  for (int k = 0; k < kSetupGroup / 64; ++k) {
-    if (k < wave) {
-      ot += s_t[k];
-      os += s_s[k];
-    }
-    tt += s_t[k];
-    ts += s_s[k];
+  Count3 tot;
+  const Count3 ex = block_excl_c3(c, s_w, &tot);
+  if (g < blocks) {  // now the block's exclusive prefix
+    B.sscr[3 * g] = ex.t;
+    B.sscr[3 * g + 1] = ex.s;
+    B.sscr[3 * g + 2] = ex.g;
   }
-  __syncthreads();
-  if (g < groups) {
-    B.grp[2 * g] = ot + it - nt;  // now the group's exclusive prefix
-    B.grp[2 * g + 1] = os + is - ns;
-  }
-  if (g == 0) {
-    B.tile_start[B.T] = tt;
-    B.sec_start[B.T] = ts;
-    if (B.offsets[0] != 0 || B.offsets[B.T] != B.total || tt > B.tiles_max ||
-        ts + B.T > B.secs_max)
-      atomicOr(&B.flags[0], 1u);
-  }
+  if (g == 0) setup_check(B, tot);
 }
 
 __global__ __launch_bounds__(kSetupGroup) void k_setup_add(Batch B) {
   const uint32_t t = blockIdx.x * kSetupGroup + threadIdx.x;
   if (t >= B.T) return;
-  B.tile_start[t] += B.grp[2 * blockIdx.x];
-  B.sec_start[t] += B.grp[2 * blockIdx.x + 1];
+  B.tile_start[t] += B.sscr[3 * blockIdx.x];
+  B.sec_start[t] += B.sscr[3 * blockIdx.x + 1];
+  B.grp_start[t] += B.sscr[3 * blockIdx.x + 2];
+}
+
+// The tiles of tile group g (a table's tiles, kScanTiles at a time):
+// [*first, *end); returns the table.
+__device__ __forceinline__ uint32_t group_tiles(const Batch &B, uint64_t g, uint64_t *first,
+                                                uint64_t *end) {
+  const uint32_t t = find_table(B.grp_start, B.T, g);
+  const uint64_t t0 = B.tile_start[t] + (g - B.grp_start[t]) * kScanTiles;
+  const uint64_t t1 = B.tile_start[t + 1];
+  *first = t0;
+  *end = (t0 + kScanTiles < t1) ? t0 + kScanTiles : t1;
+  return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -247,16 +256,18 @@ __global__ __launch_bounds__(kTileThreads) void k_reduce_tile(Batch B) {
   uint64_t off, n;
   table_range(B, t, off, n);
   const uint64_t lbase = (tile - B.tile_start[t]) * kTileItems;
-  dd s = dd_make(0.0, 0.0);
-  uint32_t bad = 0;
-#pragma unroll 4
+  double x[kItemsPerThread];
+#pragma unroll
   for (int k = 0; k < kItemsPerThread; ++k) {
     const uint64_t li = lbase + (uint64_t)k * kTileThreads + threadIdx.x;
-    if (li < n) {
-      const double x = B.w[off + li];
-      bad |= !(x >= 0.0) | (x == INFINITY);
-      s = add_d(s, x);
-    }
+    x[k] = (li < n) ? B.w[off + li] : 0.0;
+  }
+  dd s = dd_make(0.0, 0.0);
+  uint32_t bad = 0;
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    bad |= !(x[k] >= 0.0) | (x[k] == INFINITY);
+    s = add_d(s, x[k]);
   }
   bad = __any(bad) ? 1u : 0u;
   if ((threadIdx.x & 63) == 0) s_bad[threadIdx.x >> 6] = bad;
@@ -273,10 +284,43 @@ __global__ __launch_bounds__(kTileThreads) void k_reduce_tile(Batch B) {
 }
 
 // ---------------------------------------------------------------------------
-// k_finalize: per table W, W/N, status (one block per table)
+// k_reduce_group: dd sum of a tile group's tile sums (fixed order)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(Batch B) {
-  __shared__ dd s_wave[16];
+__global__ __launch_bounds__(256) void k_reduce_group(Batch B) {
+  __shared__ dd s_wave[4];
+  __shared__ uint32_t s_bad;
+  if (B.flags[0]) return;
+  const uint64_t g = blockIdx.x;
+  if (g >= B.grp_start[B.T]) return;
+  if (threadIdx.x == 0) s_bad = 0;
+  uint64_t k0, k1;
+  group_tiles(B, g, &k0, &k1);
+  __syncthreads();
+  dd s = dd_make(0.0, 0.0);
+  uint32_t bad = 0;
+  for (uint64_t k = k0 + threadIdx.x * 4; k < k0 + threadIdx.x * 4 + 4 && k < k1; ++k) {
+    const ReducePart p = B.tilew[k];
+    s = add_fast(s, dd_make(p.hi, p.lo));
+    bad |= p.bad;
+  }
+  if (bad) atomicOr(&s_bad, 1u);
+  const dd tot = block_sum_dd(s, s_wave);
+  if (threadIdx.x == 0) {
+    ReducePart p;
+    p.hi = tot.hi;
+    p.lo = tot.lo;
+    p.bad = s_bad;
+    p.pad = 0;
+    p.pad2 = 0.0;
+    B.grpw[g] = p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize: per table W, W/N, status (one block per table, over its groups)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(Batch B) {
+  __shared__ dd s_wave[4];
   __shared__ uint32_t s_bad;
   const uint32_t t = blockIdx.x;
   if (B.flags[0]) {  // inconsistent batch description: every table fails, nothing is built
@@ -289,12 +333,12 @@ __global__ __launch_bounds__(1024) void k_finalize(Batch B) {
   if (B.hdr[t].status != ALIAS_OK) return;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  const uint64_t t0 = B.tile_start[t], t1 = B.tile_start[t + 1];
+  const uint64_t g0 = B.grp_start[t], g1 = B.grp_start[t + 1];
   dd s = dd_make(0.0, 0.0);
   uint32_t bad = 0;
-  for (uint64_t k = t0 + threadIdx.x; k < t1; k += blockDim.x) {
-    const ReducePart p = B.tilew[k];
-    s = s + dd_make(p.hi, p.lo);
+  for (uint64_t k = g0 + threadIdx.x; k < g1; k += blockDim.x) {
+    const ReducePart p = B.grpw[k];
+    s = add_fast(s, dd_make(p.hi, p.lo));
     bad |= p.bad;
   }
   if (bad) atomicOr(&s_bad, 1u);
@@ -337,25 +381,28 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(Batch B) {
   table_range(B, t, off, n);
   const uint64_t lbase = (tile - B.tile_start[t]) * kTileItems;
   const dd avg = dd_make(B.hdr[t].avg_hi, B.hdr[t].avg_lo);
-  dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
-  uint32_t cnt = 0;
-#pragma unroll 4
+  double x[kItemsPerThread];
+#pragma unroll
   for (int k = 0; k < kItemsPerThread; ++k) {
     const uint64_t li = lbase + (uint64_t)k * kTileThreads + tid;
-    if (li < n) {
-      const double x = B.w[off + li];
-      const bool light = le(dd_make(x, 0.0), avg);
-      dd a = light ? acc_l : acc_h;
-      a = add_d(a, x);
-      if (light)
-        acc_l = a;
-      else
-        acc_h = a;
-      cnt += light;
-    }
+    x[k] = (li < n) ? B.w[off + li] : -1.0;  // -1: no item
   }
-  acc_l = wave_sum(acc_l);
-  acc_h = wave_sum(acc_h);
+  dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kItemsPerThread; ++k) {
+    const bool valid = x[k] >= 0.0;
+    const bool light = valid && le(dd_make(x[k], 0.0), avg);
+    dd a = light ? acc_l : acc_h;
+    a = add_d(a, valid ? x[k] : 0.0);
+    if (light)
+      acc_l = a;
+    else
+      acc_h = a;
+    cnt += light;
+  }
+  acc_l = wave_sum_fast(acc_l);
+  acc_h = wave_sum_fast(acc_h);
   cnt = wave_sum_u32(cnt);
   if (lane == 0) {
     s_l[wave] = acc_l;
@@ -367,8 +414,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(Batch B) {
     dd tl = s_l[0], th = s_h[0];
     uint32_t c = s_c[0];
     for (int k = 1; k < kTileThreads / 64; ++k) {
-      tl = tl + s_l[k];
-      th = th + s_h[k];
+      tl = add_fast(tl, s_l[k]);
+      th = add_fast(th, s_h[k]);
       c += s_c[k];
     }
     TileSum ts;
@@ -385,8 +432,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(Batch B) {
 // chunks of 4 tiles per thread; table totals; the final prefix-sum points
 // when a list length is a multiple of the stride.
 // ---------------------------------------------------------------------------
-constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 4;
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = kScanTiles / kScanThreads;  // 4 tiles per thread
 
 struct ScanVal {
   uint64_t c;
@@ -401,11 +448,12 @@ __device__ __forceinline__ ScanVal sv_zero() {
   return v;
 }
 
+// sums of nonnegative terms: same-sign additions
 __device__ __forceinline__ ScanVal sv_add(const ScanVal &a, const ScanVal &b) {
   ScanVal r;
   r.c = a.c + b.c;
-  r.l = a.l + b.l;
-  r.h = a.h + b.h;
+  r.l = add_fast(a.l, b.l);
+  r.h = add_fast(a.h, b.h);
   return r;
 }
 
@@ -417,13 +465,37 @@ __device__ __forceinline__ ScanVal sv_of(const TileSum &ts) {
   return v;
 }
 
-// exclusive scan over a 1024-thread block; *total gets the block total
-__device__ __forceinline__ ScanVal block_exscan(ScanVal v, ScanVal *s_w /*[16]*/, ScanVal *total) {
+__device__ __forceinline__ ScanVal sv_of(const TilePrefix &p) {
+  ScanVal v;
+  v.c = p.l_before;
+  v.l = p.pl;
+  v.h = p.ph;
+  return v;
+}
+
+__device__ __forceinline__ TilePrefix tp_of(const ScanVal &v) {
+  TilePrefix p;
+  p.l_before = v.c;
+  p.pad = 0;
+  p.pl = v.l;
+  p.ph = v.h;
+  return p;
+}
+
+// exclusive scan over a kScanThreads block; *total gets the block total
+__device__ __forceinline__ ScanVal block_exscan(ScanVal v, ScanVal *s_w, ScanVal *total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  ScanVal inc;
-  inc.l = wave_inclusive_scan(v.l, lane);
-  inc.h = wave_inclusive_scan(v.h, lane);
-  inc.c = wave_incl_u64(v.c, lane);
+  ScanVal inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const dd ol = shfl_up(inc.l, d), oh = shfl_up(inc.h, d);
+    const uint64_t oc = __shfl_up(inc.c, d, 64);
+    if (lane >= d) {
+      inc.l = add_fast(ol, inc.l);
+      inc.h = add_fast(oh, inc.h);
+      inc.c += oc;
+    }
+  }
   if (lane == 63) s_w[wave] = inc;
   ScanVal ex;
   ex.l = shfl_up(inc.l, 1);
@@ -441,31 +513,50 @@ __device__ __forceinline__ ScanVal block_exscan(ScanVal v, ScanVal *s_w /*[16]*/
   return sv_add(off, ex);
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_tilescan(Batch B) {
+// k_scan_group: per tile group, the exclusive prefix of its tiles' sums
+// (group-local) and the group's totals.
+__global__ __launch_bounds__(kScanThreads) void k_scan_group(Batch B) {
+  __shared__ ScanVal s_w[kScanThreads / 64];
+  if (B.flags[0]) return;
+  const uint64_t g = blockIdx.x;
+  if (g >= B.grp_start[B.T]) return;
+  uint64_t k0, k1;
+  const uint32_t t = group_tiles(B, g, &k0, &k1);
+  if (B.hdr[t].status != ALIAS_OK) return;
+  const uint64_t b = k0 + (uint64_t)threadIdx.x * kScanPer;
+  ScanVal v[kScanPer];
+  ScanVal mine = sv_zero();
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    v[u] = (b + u < k1) ? sv_of(B.tsum[b + u]) : sv_zero();
+    mine = sv_add(mine, v[u]);
+  }
+  ScanVal tot;
+  ScanVal run = block_exscan(mine, s_w, &tot);
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    if (b + u < k1) B.tpre[b + u] = tp_of(run);
+    run = sv_add(run, v[u]);
+  }
+  if (threadIdx.x == 0) B.gsum[g] = tp_of(tot);
+}
+
+// k_scan_table: per table, the exclusive prefix of its groups' totals, the
+// table's light count and sums, and the final prefix-sum points when a list
+// length is a multiple of the stride.
+__global__ __launch_bounds__(kScanThreads) void k_scan_table(Batch B) {
   __shared__ ScanVal s_w[kScanThreads / 64];
   if (B.flags[0]) return;
   const uint32_t t = blockIdx.x;
   if (B.hdr[t].status != ALIAS_OK) return;
-  const uint64_t t0 = B.tile_start[t], t1 = B.tile_start[t + 1];
+  const uint64_t g0 = B.grp_start[t], g1 = B.grp_start[t + 1];
   ScanVal carry = sv_zero();
-  for (uint64_t c0 = t0; c0 < t1; c0 += (uint64_t)kScanThreads * kScanPer) {
-    const uint64_t b = c0 + (uint64_t)threadIdx.x * kScanPer;
-    ScanVal mine = sv_zero();
-    for (int u = 0; u < kScanPer; ++u)
-      if (b + u < t1) mine = sv_add(mine, sv_of(B.tsum[b + u]));
+  for (uint64_t c0 = g0; c0 < g1; c0 += kScanThreads) {
+    const uint64_t g = c0 + threadIdx.x;
+    const ScanVal mine = (g < g1) ? sv_of(B.gsum[g]) : sv_zero();
     ScanVal tot;
-    ScanVal run = sv_add(carry, block_exscan(mine, s_w, &tot));
-    for (int u = 0; u < kScanPer; ++u) {
-      if (b + u < t1) {
-        TilePrefix p;
-        p.l_before = run.c;
-        p.pad = 0;
-        p.pl = run.l;
-        p.ph = run.h;
-        B.tpre[b + u] = p;
-        run = sv_add(run, sv_of(B.tsum[b + u]));
-      }
-    }
+    const ScanVal ex = sv_add(carry, block_exscan(mine, s_w, &tot));
+    if (g < g1) B.gpre[g] = tp_of(ex);
     carry = sv_add(carry, tot);
   }
   if (threadIdx.x == 0) {
@@ -535,20 +626,11 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
     lmask |= (uint32_t)light << u;
   }
   const uint32_t hmask = vmask & ~lmask;
-  dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
-#pragma unroll
-  for (int u = 0; u < kItemsPerThread; ++u) {
-    const bool light = (lmask >> u) & 1u;
-    dd a = light ? acc_l : acc_h;
-    a = add_d(a, ((vmask >> u) & 1u) ? x[u] : 0.0);
-    if (light)
-      acc_l = a;
-    else
-      acc_h = a;
-  }
   const uint32_t nl = __popc(lmask), nh = __popc(hmask);
 
-  // 3. block exclusive scans of the counts and sums
+  // 3a. block exclusive scans of the counts: this thread's first light and
+  //     heavy ranks, hence which of its entries (if any) falls on a prefix
+  //     point (every 64 entries of a list; at most one per list, G < 64)
   uint32_t cl_inc = nl, ch_inc = nh;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -558,61 +640,124 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
       ch_inc += b;
     }
   }
-  dd sl_inc = wave_inclusive_scan(acc_l, lane);
-  dd sh_inc = wave_inclusive_scan(acc_h, lane);
   if (lane == 63) {
     S.cl[wave] = cl_inc;
     S.ch[wave] = ch_inc;
-    S.wl[wave] = sl_inc;
-    S.wh[wave] = sh_inc;
   }
+  TilePrefix tp;
+  {
+    // tile's prefix within its table = its group's prefix + its prefix in the group
+    const uint64_t lt = tile - B.tile_start[t];
+    const TilePrefix gp = B.gpre[B.grp_start[t] + lt / kScanTiles];
+    tp = tp_of(sv_add(sv_of(gp), sv_of(B.tpre[tile])));
+  }
+  const uint64_t l_before = tp.l_before;          // table-local
+  const uint64_t h_before = lbase - l_before;     // table-local
   __syncthreads();  // also: every thread has its x[] in registers
   uint32_t cl_off = 0, ch_off = 0, Lt = 0;
-  dd sl_off = dd_make(0.0, 0.0), sh_off = dd_make(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (k < wave) {
       cl_off += S.cl[k];
       ch_off += S.ch[k];
-      sl_off = sl_off + S.wl[k];
-      sh_off = sh_off + S.wh[k];
     }
     Lt += S.cl[k];
+  }
+  const uint32_t rl0 = cl_off + cl_inc - nl;        // tile-local rank of the first light
+  const uint32_t rh0 = ch_off + ch_inc - nh;        // ... and of the first heavy
+  const uint32_t kl = (uint32_t)((kAggStride - ((l_before + rl0) & (kAggStride - 1))) & (kAggStride - 1));
+  const uint32_t kh = (uint32_t)((kAggStride - ((h_before + rh0) & (kAggStride - 1))) & (kAggStride - 1));
+
+  // 3b. running sums of both lists; the sum before the prefix-point entry
+  //     (the kl-th light, the kh-th heavy of this thread) is kept.  The
+  //     weights are read from LDS again here, after the barrier: kept in
+  //     registers, the compiler would run this chain before the barrier and
+  //     hold every partial sum until kl and kh are known.
+#pragma unroll
+  for (int u = 0; u < kItemsPerThread; ++u) x[u] = S.val[spos(tid * kItemsPerThread + u)];
+  int ul = -1, uh = -1;  // positions of those entries among the thread's items
+  {
+    uint32_t cl = 0, ch = 0;
+#pragma unroll
+    for (int u = 0; u < kItemsPerThread; ++u) {
+      const uint32_t light = (lmask >> u) & 1u, heavy = (hmask >> u) & 1u;
+      ul = (light && cl == kl) ? u : ul;
+      uh = (heavy && ch == kh) ? u : uh;
+      cl += light;
+      ch += heavy;
+    }
+  }
+  dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
+  dd snap_l = dd_make(0.0, 0.0), snap_h = dd_make(0.0, 0.0);
+#pragma unroll
+  for (int u = 0; u < kItemsPerThread; ++u) {
+    const bool light = (lmask >> u) & 1u;
+    if (u == ul) snap_l = acc_l;
+    if (u == uh) snap_h = acc_h;
+    // materialise the snapshots here (an empty asm statement the compiler
+    // must assume reads and rewrites them); otherwise it keeps every partial
+    // sum live and selects among them after the loop
+    asm volatile("" : "+v"(snap_l.hi), "+v"(snap_l.lo), "+v"(snap_h.hi), "+v"(snap_h.lo));
+    dd a = light ? acc_l : acc_h;
+    a = add_d(a, ((vmask >> u) & 1u) ? x[u] : 0.0);
+    if (light)
+      acc_l = a;
+    else
+      acc_h = a;
+  }
+
+  // 3c. block exclusive scans of the sums (sums of nonnegative terms, so the
+  //     same-sign addition add_fast is accurate)
+  dd sl_inc = acc_l, sh_inc = acc_h;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const dd ol = shfl_up(sl_inc, d), oh = shfl_up(sh_inc, d);
+    if (lane >= d) {
+      sl_inc = add_fast(ol, sl_inc);
+      sh_inc = add_fast(oh, sh_inc);
+    }
+  }
+  if (lane == 63) {
+    S.wl[wave] = sl_inc;
+    S.wh[wave] = sh_inc;
+  }
+  __syncthreads();
+  dd sl_off = dd_make(0.0, 0.0), sh_off = dd_make(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < wave) {
+      sl_off = add_fast(sl_off, S.wl[k]);
+      sh_off = add_fast(sh_off, S.wh[k]);
+    }
   }
   dd sl_lane = shfl_up(sl_inc, 1), sh_lane = shfl_up(sh_inc, 1);
   if (lane == 0) {
     sl_lane = dd_make(0.0, 0.0);
     sh_lane = dd_make(0.0, 0.0);
   }
-  const TilePrefix tp = B.tpre[tile];
-  const uint64_t l_before = tp.l_before;          // table-local
-  const uint64_t h_before = lbase - l_before;     // table-local
-  const dd pl_thr = tp.pl + (sl_off + sl_lane);
-  const dd ph_thr = tp.ph + (sh_off + sh_lane);
   const uint64_t ab = agg_base(off, t);
-  uint32_t rl = cl_off + cl_inc - nl;
-  uint32_t rh = Lt + ch_off + ch_inc - nh;
+  if (kl < nl) {
+    const uint64_t g = l_before + rl0 + kl;
+    B.agg_l[ab + g / kAggStride] = add_fast(add_fast(tp.pl, add_fast(sl_off, sl_lane)), snap_l);
+  }
+  if (kh < nh) {
+    const uint64_t g = h_before + rh0 + kh;
+    B.agg_h[ab + g / kAggStride] = add_fast(add_fast(tp.ph, add_fast(sh_off, sh_lane)), snap_h);
+  }
 
-  // 4. stage entries at their tile-local ranks; emit prefix sums every 64
-  dd run_l = dd_make(0.0, 0.0), run_h = dd_make(0.0, 0.0);
+  // 4. stage entries at their tile-local ranks (lights first, then heavies)
+  uint32_t rl = rl0, rh = Lt + rh0;
+  const uint32_t li0 = (uint32_t)(lbase + (uint64_t)tid * kItemsPerThread);
 #pragma unroll
   for (int u = 0; u < kItemsPerThread; ++u) {
-    const uint32_t li = (uint32_t)(lbase + (uint64_t)tid * kItemsPerThread + u);
-    if ((lmask >> u) & 1u) {
-      const uint64_t g = l_before + rl;
-      S.idx[rl] = li;
-      S.val[rl] = x[u];
-      if ((g & (kAggStride - 1)) == 0) B.agg_l[ab + g / kAggStride] = pl_thr + run_l;
-      run_l = add_d(run_l, x[u]);
-      ++rl;
-    } else if ((hmask >> u) & 1u) {
-      const uint64_t g = h_before + (rh - Lt);
-      S.idx[rh] = li;
-      S.val[rh] = x[u];
-      if ((g & (kAggStride - 1)) == 0) B.agg_h[ab + g / kAggStride] = ph_thr + run_h;
-      run_h = add_d(run_h, x[u]);
-      ++rh;
+    const uint32_t light = (lmask >> u) & 1u, valid = (vmask >> u) & 1u;
+    const uint32_t dst = light ? rl : rh;
+    if (valid) {
+      S.idx[dst] = li0 + u;
+      S.val[dst] = x[u];
     }
+    rl += light;
+    rh += valid & (light ^ 1u);
   }
   __syncthreads();
 
@@ -769,69 +914,47 @@ __global__ __launch_bounds__(256) void k_split(Batch B) {
 }
 
 // ---------------------------------------------------------------------------
-// k_pack: one wave per section of C rows (Sec. 4.2).
-//   1. stage the section's light and heavy entries (weight, id) in LDS with
-//      coalesced loads (the paper's shared-memory pack with weights in l/h);
-//   2. prefix sums every S = min(16, C/64) entries of both lists;
-//   3. each lane finds its start state at local row G*lane (G = C/64) by a
-//      search on those sums and a walk of fewer than S entries;
-//   4. each lane sweeps its G rows in LDS: a light row records its alias, a
-//      closing heavy records the light index at which it closed; the
-//      residual advances by (incoming weight - W/N) either way;
-//   5. heavy rows are finished in parallel: residual at closing from the
-//      prefix sums, prob = residual / (W/N), alias = next heavy;
-//   6. light rows are written in light (near item) order: prob = w / (W/N)
-//      and the recorded alias.  Every table row is written exactly once.
+// k_pack: one block of P threads packs one section of C rows (Sec. 4.2),
+// G = C / P rows per thread.
+//
+// Inside a section the sweep is a merge.  With i lights and j heavies of the
+// section used, the current heavy's residual is
+//   r(i, j) = Bo + IH[j] + SL[i] - (i + j) * avg,
+// where SL[i] is the sum of the section's first i lights, IH[j] the sum of
+// its heavies 0..j, and Bo = spill - w(heavy 0) (the residual of heavy 0 at
+// the section start is the spill).  The sweep closes heavy j iff
+// r(i, j) <= avg, i.e. iff B_j <= C_i with B_j = Bo + IH[j] - j * avg and
+// C_i = (i + 1) * avg - SL[i].  B increases with j (a heavy weighs more than
+// avg) and C does not decrease with i (a light weighs at most avg), so the
+// sweep is the merge of two sorted sequences with ties going to B, and each
+// thread finds the state at its first row G * t by a merge-path search and
+// then merges its G rows independently of the others.
+//   1. entries (lights, then the heavies closed here) are loaded G per
+//      thread; their ids go to LDS;
+//   2. inclusive dd prefix sums of the two lists: one segmented block scan;
+//   3. merge-path search, then G merge steps.  Each comparison is made in
+//      binary64 on the high parts first, with a rigorous bound on its
+//      rounding error; only a comparison inside the bound is repeated in dd;
+//   4. rows: a light gets prob = w / avg and the heavy it was packed with; a
+//      heavy closed after i lights gets prob = r(i, j) / avg (dd) and the
+//      next heavy as alias.  Every table row is written exactly once.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int ppos(int e) { return e + (e >> 4); }  // padded LDS index
 
 struct PackLds {
-  uint32_t w_off, q_off, ix_off, ao_off, bytes, nq;
+  uint32_t ie_off, ix_off, ao_off, bytes;
 };
 
-__host__ __device__ inline int pack_stride(uint32_t chunk) {
-  const int G = (int)(chunk >> 6);
-  return G < 16 ? G : 16;
-}
-
+// LDS of one section: prefix sums (dd) of up to C entries, ids of up to C+1
+// entries, the merge record of up to C entries.
 __host__ __device__ inline PackLds pack_lds(uint32_t chunk) {
   PackLds p;
-  const uint32_t nw = (uint32_t)ppos((int)chunk + 2) + 1;
-  p.nq = chunk / (uint32_t)pack_stride(chunk) + 2;
-  p.w_off = 0;
-  p.q_off = (8u * nw + 15u) & ~15u;
-  p.ix_off = p.q_off + 16u * 2u * p.nq;
-  p.ao_off = p.ix_off + 4u * nw;
-  p.bytes = (p.ao_off + 4u * nw + 15u) & ~15u;
+  const uint32_t ne = (uint32_t)ppos((int)chunk + 1) + 1;
+  p.ie_off = 0;
+  p.ix_off = 16u * ne;
+  p.ao_off = p.ix_off + ((4u * ne + 15u) & ~15u);
+  p.bytes = p.ao_off + ((4u * ne + 15u) & ~15u);
   return p;
-}
-
-// Prefix sums every S entries of one staged list: Q[q] = sum of the first
-// min(q*S, cnt) entries, for q = 0 .. C/S.  Lane t owns entries [tG, tG+G).
-__device__ __forceinline__ void pack_prefix(const double *Wv, int off, int cnt, dd *Q, int G,
-                                            int S, int lane) {
-  const int b = lane * G;
-  dd acc = dd_make(0.0, 0.0);
-  dd part[2];  // partial sums at the lane's stride points (G/S <= 2)
-  const int per = G / S;
-  for (int u = 0; u < G; ++u) {
-    if ((u % S) == 0 && (u / S) < 2) part[u / S] = acc;
-    if (b + u < cnt) acc = add_d(acc, Wv[ppos(off + b + u)]);
-  }
-  const dd inc = wave_inclusive_scan(acc, lane);
-  dd ex = shfl_up(inc, 1);
-  if (lane == 0) ex = dd_make(0.0, 0.0);
-  for (int k = 0; k < per && k < 2; ++k) Q[(b / S) + k] = ex + part[k];
-  if (lane == 63) Q[(64 * G) / S] = inc;
-}
-
-// sigma of the first p entries of a staged list, from the stride points and
-// fewer than S entries.
-__device__ __forceinline__ dd pack_sigma(const double *Wv, int off, const dd *Q, int S, int p) {
-  const int q = p / S;
-  dd sgm = Q[q];
-  for (int e = q * S; e < p; ++e) sgm = add_d(sgm, Wv[ppos(off + e)]);
-  return sgm;
 }
 
 // Table output: two arrays (prob, alias) or one array of 16-byte rows.
@@ -855,28 +978,64 @@ __device__ __forceinline__ void put_row(const TableOut &t, uint64_t item, double
   }
 }
 
-template <bool kRows>
-__global__ __launch_bounds__(64 * kPackWaves) void k_pack(Batch B, TableOut out) {
+// Section-local merge state shared by the comparison helpers.
+struct Merge {
+  const dd *IE;  // inclusive prefix sums: lights at [0, nl), heavies at [nl, nl + nh)
+  dd Bo, avg;
+  int nl;
+};
+
+// SL[i]: sum of the first i lights (i <= nl)
+__device__ __forceinline__ dd merge_sl(const Merge &M, int i) {
+  return i > 0 ? M.IE[ppos(i - 1)] : dd_make(0.0, 0.0);
+}
+
+// r(i, j) in dd
+__device__ __forceinline__ dd merge_r(const Merge &M, int i, int j) {
+  return ((M.Bo + M.IE[ppos(M.nl + j)]) + merge_sl(M, i)) - mul_d(M.avg, (double)(i + j));
+}
+
+// Does the sweep at state (i, j), i < nl, close heavy j?  I.e. r(i, j) <= avg,
+// D = Bo + IH[j] + SL[i] - (i + j + 1) * avg <= 0.
+// Binary64 filter: each of the four terms carries a relative error of at
+// most u = 2^-53 from dropping the low parts (2u for the product with avg),
+// and the three additions add at most u times the running magnitude each, so
+// |D - Dd| <= 5u * mag.  When |Dd| exceeds 8u * mag the sign of Dd is the
+// sign of D; otherwise (ties, near-ties, tiny magnitudes) D is formed in dd.
+__device__ __forceinline__ bool merge_close(const Merge &M, int i, int j) {
+  const double a = M.Bo.hi;
+  const double b = M.IE[ppos(M.nl + j)].hi;
+  const double c = i > 0 ? M.IE[ppos(i - 1)].hi : 0.0;
+  const double d = (double)(i + j + 1) * M.avg.hi;
+  const double Dd = ((a + b) + c) - d;
+  const double mag = (fabs(a) + b) + (c + d);
+  if (mag > 0x1p-900 && fabs(Dd) > 0x1p-50 * mag) return Dd < 0.0;
+  const dd D = merge_r(M, i, j) - M.avg;
+  return D.hi < 0.0 || (D.hi == 0.0 && D.lo <= 0.0);
+}
+
+template <bool kRows, int kG>
+__global__ __launch_bounds__(256) void k_pack(Batch B, TableOut out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ dd s_wv[4];
+  __shared__ int s_wf[4];
+  __shared__ int s_wi[4], s_wj[4];
   if (B.flags[0]) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t gsec = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  const int P = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t gsec = blockIdx.x;
   if (gsec >= B.sec_start[B.T]) return;
   const uint32_t t = find_table(B.sec_start, B.T, gsec);
   const alias_ws_header &hdr = B.hdr[t];
   if (hdr.status != ALIAS_OK) return;
   const uint32_t chunk = B.chunk;
   const PackLds PLy = pack_lds(chunk);
-  unsigned char *base = smem_raw + (size_t)wave * PLy.bytes;
-  double *Wv = (double *)(base + PLy.w_off);
-  dd *QL = (dd *)(base + PLy.q_off);
-  dd *QH = QL + PLy.nq;
-  uint32_t *Ix = (uint32_t *)(base + PLy.ix_off);
-  uint32_t *Ao = (uint32_t *)(base + PLy.ao_off);
+  dd *IE = (dd *)(smem_raw + PLy.ie_off);
+  uint32_t *Ix = (uint32_t *)(smem_raw + PLy.ix_off);
+  uint32_t *Ao = (uint32_t *)(smem_raw + PLy.ao_off);
 
   uint64_t off, n;
   table_range(B, t, off, n);
-  const uint64_t bnd = gsec + t;  // this section's first boundary: sec_start[t] + t + local
+  const uint64_t bnd = gsec + t;  // this section's first boundary
   const uint32_t *l_idx = B.l_idx + off, *h_idx = B.h_idx + off;
   const double *l_w = B.l_w + off, *h_w = B.h_w + off;
   const uint64_t H = hdr.H;
@@ -886,131 +1045,169 @@ __global__ __launch_bounds__(64 * kPackWaves) void k_pack(Batch B, TableOut out)
   const int nl = (int)((int64_t)i1 - (int64_t)i0), nh = (int)((int64_t)j1 - (int64_t)j0);
   // i + j = m at every boundary, so nl + nh is the section's row count; a
   // negative part would mean inconsistent splits: report, write nothing.
-  if (nl < 0 || nh < 0 || nl + nh > (int)chunk) {
-    if (lane == 0) B.status[t] = ALIAS_EINTERNAL;
+  if (nl < 0 || nh < 0 || nl + nh > (int)chunk || nl + nh > P * kG) {
+    if (tid == 0) B.status[t] = ALIAS_EINTERNAL;
     return;
   }
   const Divisor dv = make_divisor(avg);
-  if (j0 >= H) {  // no heavy item left: remaining lights keep their whole row
-    for (int e = lane; e < nl; e += 64) {
+  if (j0 >= H) {  // no heavy item left: the remaining lights keep their whole row
+    for (int e = tid; e < nl; e += P) {
       const uint32_t l = l_idx[i0 + e];
       put_row<kRows>(out, off + l, clamp01(quot_fast(dd_make(l_w[i0 + e], 0.0), dv)), l);
     }
     return;
   }
-  const int nhl = (nh + 1 < (int)(H - j0)) ? nh + 1 : (int)(H - j0);
-  const int G = (int)(chunk >> 6);  // rows per lane
-  const int S = pack_stride(chunk);  // prefix-sum stride
+  const int ne = nl + nh;                   // weights: lights, then heavies 0..nh-1
+  const bool has_next = j0 + nh < H;        // heavy nh: alias of the last closed heavy
+  const int e0 = tid * kG;
 
-  // 1. stage lights in slots [0, nl), heavies in [nl, nl + nhl)
-  for (int e = lane; e < nl; e += 64) {
-    Wv[ppos(e)] = l_w[i0 + e];
-    Ix[ppos(e)] = l_idx[i0 + e];
+  // 1. entries, G consecutive per thread
+  double w[kG];
+#pragma unroll
+  for (int u = 0; u < kG; ++u) {
+    const int e = e0 + u;
+    w[u] = 0.0;
+    if (e < nl) {
+      w[u] = l_w[i0 + e];
+      Ix[ppos(e)] = l_idx[i0 + e];
+    } else if (e < ne) {
+      w[u] = h_w[j0 + (e - nl)];
+      Ix[ppos(e)] = h_idx[j0 + (e - nl)];
+    }
   }
-  for (int e = lane; e < nhl; e += 64) {
-    Wv[ppos(nl + e)] = h_w[j0 + e];
-    Ix[ppos(nl + e)] = h_idx[j0 + e];
+  if (tid == 0 && has_next) Ix[ppos(ne)] = h_idx[j0 + nh];
+
+  // 2. segmented scan: the heavy list starts a new sum at entry nl
+  dd v = dd_make(0.0, 0.0);
+  int f = 0;
+#pragma unroll
+  for (int u = 0; u < kG; ++u) {
+    const int e = e0 + u;
+    if (e < ne) {
+      if (e == nl) {
+        v = dd_make(0.0, 0.0);
+        f = 1;
+      }
+      v = add_d(v, w[u]);
+    }
   }
-  wave_lds_sync();
-
-  // 2. prefix sums every S entries
-  pack_prefix(Wv, 0, nl, QL, G, S, lane);
-  pack_prefix(Wv, nl, nhl, QH, G, S, lane);
-  wave_lds_sync();
-
-  const dd sp0 = B.spill[bnd];
-  const dd Bo = sp0 - dd_make(Wv[ppos(nl)], 0.0);  // local f(i, j) + Bo - m*avg = global f - m*avg
-  const int total = nl + nh;
-
-  // 3. this lane's start state at local row m = G*lane
-  int i, j;
-  dd r = dd_make(0.0, 0.0);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const dd ov = shfl_up(v, d);
+    const int of = __shfl_up(f, d, 64);
+    if (lane >= d) {
+      if (!f) v = add_fast(ov, v);
+      f |= of;
+    }
+  }
+  if (lane == 63) {
+    s_wv[wave] = v;
+    s_wf[wave] = f;
+  }
+  dd cv = shfl_up(v, 1);
+  int cf = __shfl_up(f, 1, 64);
+  if (lane == 0) {
+    cv = dd_make(0.0, 0.0);
+    cf = 0;
+  }
+  __syncthreads();
   {
-    const int m = G * lane;
-    if (m >= total) {
+    dd wv = dd_make(0.0, 0.0);  // combined totals of the earlier waves
+    for (int k = 0; k < wave; ++k) wv = s_wf[k] ? s_wv[k] : add_fast(wv, s_wv[k]);
+    if (!cf) cv = add_fast(wv, cv);
+  }
+  {
+    dd run = cv;
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      const int e = e0 + u;
+      if (e < ne) {
+        if (e == nl) run = dd_make(0.0, 0.0);
+        run = add_d(run, w[u]);
+        IE[ppos(e)] = run;
+      }
+    }
+  }
+  __syncthreads();
+
+  Merge M;
+  M.IE = IE;
+  M.avg = avg;
+  M.nl = nl;
+  M.Bo = add_d(B.spill[bnd], -h_w[j0]);  // j0 < H here
+
+  // 3. merge-path search for the state at row m = G * tid
+  int i, j;
+  {
+    const int m = e0;
+    if (m >= ne) {
       i = nl;
       j = nh;
-    } else if (m == 0) {
-      i = 0;
-      j = 0;
-      r = sp0;
     } else {
-      const dd target = mul_d(avg, (double)m) - Bo;
-      const int jlo = (m > nl) ? m - nl : 0;
-      const int jhi = (m < nh) ? m : nh;
-      const int qa = (jlo + S - 1) / S, qb = jhi / S;
-      const int mq = m / S;
-      int lo = qa - 1, hi = qb;
+      const int jlo = m > nl ? m - nl : 0;
+      const int jhi = m < nh ? m : nh;
+      int lo = jlo, hi = jhi;  // j = jlo is always feasible
       while (lo < hi) {
-        const int mid = lo + (hi - lo + 1) / 2;
-        if (le(QL[mq - mid] + QH[mid], target))
+        const int mid = lo + (hi - lo + 1) / 2;  // mid > jlo, so m - mid < nl
+        if (merge_close(M, m - mid, mid - 1))
           lo = mid;
         else
           hi = mid - 1;
       }
-      int ja, jb;
-      dd g;
-      if (lo >= qa) {
-        ja = lo * S;
-        jb = ja + S - 1;
-        g = QL[mq - lo] + QH[lo];
-      } else {
-        ja = jlo;
-        jb = qa * S - 1;
-        g = pack_sigma(Wv, 0, QL, S, m - jlo) + pack_sigma(Wv, nl, QH, S, jlo);
-      }
-      if (jb > jhi) jb = jhi;
-      int jj = ja;
-      while (jj < jb) {
-        const dd g2 = add_d(add_d(g, Wv[ppos(nl + jj)]), -Wv[ppos(m - jj - 1)]);
-        if (!le(g2, target)) break;
-        g = g2;
-        ++jj;
-      }
-      j = jj;
-      i = m - jj;
-      if (j0 + (uint64_t)j < H) r = (add_d(g, Wv[ppos(nl + j)]) + Bo) - mul_d(avg, (double)m);
+      j = lo;
+      i = m - lo;
     }
   }
   int ie = __shfl_down(i, 1, 64), je = __shfl_down(j, 1, 64);
+  if (lane == 0) {
+    s_wi[wave] = i;
+    s_wj[wave] = j;
+  }
+  __syncthreads();
   if (lane == 63) {
-    ie = nl;
-    je = nh;
-  }
-
-  // 4. the sweep: lights record their alias, closing heavies their light index
-  const dd navg = -avg;
-  while (i < ie || j < je) {
-    const uint64_t jg = j0 + (uint64_t)j;
-    const bool closing = (j < je) && (i == ie || le(r, avg));
-    double x;
-    if (closing) {
-      Ao[ppos(nl + j)] = (uint32_t)i;
-      x = (jg + 1 < H) ? Wv[ppos(nl + j + 1)] : 0.0;
+    if (wave + 1 < (P >> 6)) {
+      ie = s_wi[wave + 1];
+      je = s_wj[wave + 1];
     } else {
-      Ao[ppos(i)] = (jg < H) ? Ix[ppos(nl + j)] : Ix[ppos(i)];
-      x = Wv[ppos(i)];
+      ie = nl;
+      je = nh;
     }
-    r = add_fast(r, add_d(navg, x));  // residual += incoming weight - W/N
-    i += closing ? 0 : 1;
-    j += closing ? 1 : 0;
   }
-  wave_lds_sync();
-
-  // 5. heavy rows: residual at closing from the prefix sums
-  for (int e = lane; e < nh; e += 64) {
-    const int ic = (int)Ao[ppos(nl + e)];
-    const dd rc = (pack_sigma(Wv, 0, QL, S, ic) + pack_sigma(Wv, nl, QH, S, e + 1) + Bo) -
-                  mul_d(avg, (double)(ic + e));
-    const uint32_t hh = Ix[ppos(nl + e)];
-    put_row<kRows>(out, off + hh, clamp01(quot_fast(rc, dv)),
-                   (j0 + (uint64_t)e + 1 < H) ? Ix[ppos(nl + e + 1)] : hh);
+  //    the thread's G merge steps
+  while (i < ie || j < je) {
+    bool close;
+    if (j >= je)
+      close = false;
+    else if (i >= ie)
+      close = true;
+    else
+      close = merge_close(M, i, j);
+    if (close) {
+      Ao[ppos(nl + j)] = (uint32_t)i;
+      ++j;
+    } else {
+      Ao[ppos(i)] = (j0 + (uint64_t)j < H) ? Ix[ppos(nl + j)] : Ix[ppos(i)];
+      ++i;
+    }
   }
+  __syncthreads();
 
-  // 6. light rows, in light (near item) order: own share w/avg and alias
-  for (int e = lane; e < nl; e += 64)
-    put_row<kRows>(out, off + Ix[ppos(e)], clamp01(quot_fast(dd_make(Wv[ppos(e)], 0.0), dv)),
-                   Ao[ppos(e)]);
+  // 4. rows of this thread's entries
+#pragma unroll
+  for (int u = 0; u < kG; ++u) {
+    const int e = e0 + u;
+    if (e < nl) {
+      put_row<kRows>(out, off + Ix[ppos(e)], clamp01(quot_fast(dd_make(w[u], 0.0), dv)),
+                     Ao[ppos(e)]);
+    } else if (e < ne) {
+      const int k = e - nl;
+      const int ic = min((int)Ao[ppos(e)], nl);
+      const dd r = merge_r(M, ic, k);
+      const uint32_t hh = Ix[ppos(e)];
+      put_row<kRows>(out, off + hh, clamp01(quot_fast(r, dv)),
+                     (j0 + (uint64_t)k + 1 < H) ? Ix[ppos(e + 1)] : hh);
+    }
+  }
 }
 
 __global__ void k_reset_fallbacks(Batch B) {
@@ -1056,11 +1253,15 @@ static Batch make_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n
   B.hdr = (alias_ws_header *)(ws + Lo.pub.header);
   B.tile_start = (uint64_t *)(ws + Lo.tile_start);
   B.sec_start = (uint64_t *)(ws + Lo.sec_start);
+  B.grp_start = (uint64_t *)(ws + Lo.grp_start);
   B.flags = (uint32_t *)(ws + Lo.flags);
-  B.grp = (uint64_t *)(ws + Lo.grp);
+  B.sscr = (uint64_t *)(ws + Lo.sscr);
   B.tilew = (ReducePart *)(ws + Lo.tilew);
+  B.grpw = (ReducePart *)(ws + Lo.grpw);
   B.tsum = (TileSum *)(ws + Lo.tilesum);
   B.tpre = (TilePrefix *)(ws + Lo.tilepre);
+  B.gsum = (TilePrefix *)(ws + Lo.grpsum);
+  B.gpre = (TilePrefix *)(ws + Lo.grppre);
   B.l_idx = (uint32_t *)(ws + Lo.pub.l_idx);
   B.h_idx = (uint32_t *)(ws + Lo.pub.h_idx);
   B.l_w = (double *)(ws + Lo.pub.l_w);
@@ -1076,16 +1277,17 @@ static Batch make_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n
   B.model_stride = model_stride;
   B.tiles_max = Lo.tiles_max;
   B.secs_max = Lo.secs_max;
+  B.groups_max = Lo.groups_max;
   return B;
 }
 
 static void launch_setup(const Batch &B, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, B.flags);
-  const uint32_t groups = (B.T + kSetupGroup - 1) / kSetupGroup;
-  hipLaunchKernelGGL(k_setup_local, dim3(groups), dim3(kSetupGroup), 0, st, B, groups == 1);
-  if (groups > 1) {
-    hipLaunchKernelGGL(k_setup_groups, dim3(1), dim3(kSetupGroup), 0, st, B, groups);
-    hipLaunchKernelGGL(k_setup_add, dim3(groups), dim3(kSetupGroup), 0, st, B);
+  const uint32_t blocks = (B.T + kSetupGroup - 1) / kSetupGroup;
+  hipLaunchKernelGGL(k_setup_local, dim3(blocks), dim3(kSetupGroup), 0, st, B, blocks == 1);
+  if (blocks > 1) {
+    hipLaunchKernelGGL(k_setup_groups, dim3(1), dim3(kSetupGroup), 0, st, B, blocks);
+    hipLaunchKernelGGL(k_setup_add, dim3(blocks), dim3(kSetupGroup), 0, st, B);
   }
 }
 
@@ -1102,29 +1304,45 @@ int launch_build_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n1
       make_batch(d_w, d_offsets, n1, d_ws, d_status, Lo, models, model_bytes, model_stride);
   const uint32_t tiles = (uint32_t)Lo.tiles_max;
   launch_setup(B, st);
+  const uint32_t groups = (uint32_t)Lo.groups_max;
   hipLaunchKernelGGL(k_reduce_tile, dim3(tiles), dim3(kTileThreads), 0, st, B);
-  hipLaunchKernelGGL(k_finalize, dim3(B.T), dim3(1024), 0, st, B);
+  hipLaunchKernelGGL(k_reduce_group, dim3(groups), dim3(256), 0, st, B);
+  hipLaunchKernelGGL(k_finalize, dim3(B.T), dim3(256), 0, st, B);
   hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, B);
-  hipLaunchKernelGGL(k_tilescan, dim3(B.T), dim3(kScanThreads), 0, st, B);
+  hipLaunchKernelGGL(k_scan_group, dim3(groups), dim3(kScanThreads), 0, st, B);
+  hipLaunchKernelGGL(k_scan_table, dim3(B.T), dim3(kScanThreads), 0, st, B);
   hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, B);
   launch_split(B, st);
-  // one wave per section; as many waves per block as the LDS allows (<= 4)
-  const size_t per_wave = pack_lds(Lo.chunk).bytes;
-  const size_t max_lds = device_max_lds_per_block();
-  size_t waves = max_lds / per_wave;
-  if (waves > (size_t)kPackWaves) waves = kPackWaves;
-  if (Lo.pack_waves && Lo.pack_waves < waves) waves = Lo.pack_waves;
-  if (waves == 0) return ALIAS_EINVAL;
+  // one block per section: P = 64 * waves threads, G = C / P rows per thread
+  const uint32_t waves = pack_waves_for(Lo.chunk, Lo.pack_waves);
+  const uint32_t P = 64u * waves, G = Lo.chunk / P;
+  const size_t lds = pack_lds(Lo.chunk).bytes;
+  if (waves == 0 || lds > device_max_lds_per_block()) return ALIAS_EINVAL;
   TableOut out;
   out.prob = d_prob;
   out.alias = d_alias;
   out.rows = d_rows;
-  const uint32_t pblocks = (uint32_t)((Lo.secs_max + waves - 1) / waves);
-  if (d_rows)
-    hipLaunchKernelGGL(k_pack<true>, dim3(pblocks), dim3(64 * waves), waves * per_wave, st, B, out);
-  else
-    hipLaunchKernelGGL(k_pack<false>, dim3(pblocks), dim3(64 * waves), waves * per_wave, st, B,
-                       out);
+  const dim3 grid((uint32_t)Lo.secs_max), block(P);
+#define ALIAS_PACK_LAUNCH(R, GG) \
+  hipLaunchKernelGGL((k_pack<R, GG>), grid, block, lds, st, B, out)
+  if (d_rows) {
+    switch (G) {
+      case 1: ALIAS_PACK_LAUNCH(true, 1); break;
+      case 2: ALIAS_PACK_LAUNCH(true, 2); break;
+      case 4: ALIAS_PACK_LAUNCH(true, 4); break;
+      case 8: ALIAS_PACK_LAUNCH(true, 8); break;
+      default: return ALIAS_EINVAL;
+    }
+  } else {
+    switch (G) {
+      case 1: ALIAS_PACK_LAUNCH(false, 1); break;
+      case 2: ALIAS_PACK_LAUNCH(false, 2); break;
+      case 4: ALIAS_PACK_LAUNCH(false, 4); break;
+      case 8: ALIAS_PACK_LAUNCH(false, 8); break;
+      default: return ALIAS_EINVAL;
+    }
+  }
+#undef ALIAS_PACK_LAUNCH
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 

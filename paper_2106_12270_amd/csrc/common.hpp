@@ -17,8 +17,7 @@ constexpr int kReduceMaxBlocks = 1024;
 constexpr uint32_t kDefaultChunk = 1024;
 constexpr uint32_t kMinChunk = 64;
 constexpr uint32_t kMaxChunk = 2048;
-constexpr int kPackWaves = 4;            // sections per pack block (one wave each)
-constexpr int kScanGroup = 1024;         // tiles per block of the tile scan
+constexpr int kScanTiles = 1024;         // tiles per group of the two-level tile reductions and scans
 
 // One table row in the packed layout: 16 bytes, loaded and stored with a
 // single 128-bit access.
@@ -55,12 +54,16 @@ struct Layout {
   alias_ws_layout pub;  // offsets of the arrays shared with the public view
   uint64_t tile_start;  // uint64[T+1]: first tile of each table
   uint64_t sec_start;   // uint64[T+1]: first section of each table
+  uint64_t grp_start;   // uint64[T+1]: first tile group of each table
   uint64_t tilew;       // ReducePart per tile
+  uint64_t grpw;        // ReducePart per tile group
   uint64_t tilesum;     // TileSum per tile
-  uint64_t tilepre;     // TilePrefix per tile (within its table)
-  uint64_t grp;         // setup scratch: uint64[2 * groups]
+  uint64_t tilepre;     // TilePrefix per tile (within its group)
+  uint64_t grpsum;      // TilePrefix per group: the group's totals
+  uint64_t grppre;      // TilePrefix per group: exclusive prefix within its table
+  uint64_t sscr;        // setup scratch: uint64[3 * setup blocks]
   uint64_t flags;       // uint32[16]: [0] = inconsistent batch description
-  uint64_t tiles_max, secs_max, total;
+  uint64_t tiles_max, secs_max, groups_max, total;
   uint32_t T, chunk, pack_waves;
 };
 
@@ -69,6 +72,18 @@ constexpr int kSetupGroup = 1024;
 
 __host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// Waves that pack one section together (one block per section): the
+// requested number, or min(4, C/64); 0 if the request is invalid.  Each
+// thread packs G = C / (64 * waves) rows, G in {1, 2, 4, 8}.
+inline uint32_t pack_waves_for(uint32_t chunk, uint32_t requested) {
+  uint32_t w = requested ? requested : (chunk / 64 < 4 ? chunk / 64 : 4);
+  if (w != 1 && w != 2 && w != 4) return 0;
+  const uint32_t P = 64 * w;
+  if (chunk % P) return 0;
+  const uint32_t G = chunk / P;
+  return (G == 1 || G == 2 || G == 4 || G == 8) ? w : 0;
+}
+
 // Computes the workspace layout; returns false for invalid arguments.
 inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_opts *o, Layout *L) {
   if (T == 0 || T > kMaxTables || total == 0 || total > (1ull << 40)) return false;
@@ -76,15 +91,16 @@ inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_o
   if (o) {
     if (o->chunk_items) chunk = o->chunk_items;
     if (o->split_method > ALIAS_SPLIT_LEARNED) return false;
-    if (o->pack_waves > (uint32_t)kPackWaves) return false;
     waves = o->pack_waves;
     if (o->reserved) return false;
   }
   if (chunk < kMinChunk || chunk > kMaxChunk || (chunk & (chunk - 1))) return false;
+  if (pack_waves_for(chunk, waves) == 0) return false;
   const uint64_t tiles = (total + kTileItems - 1) / kTileItems + T;
   // section boundaries: sum over tables of (ceil(n_t / C) + 1) <= total/C + 2T
   const uint64_t secs = (total + chunk - 1) / chunk + 2ull * T;
-  const uint64_t groups = (T + kSetupGroup - 1) / kSetupGroup;
+  const uint64_t grps = tiles / kScanTiles + 1 + T;
+  const uint64_t sblocks = (T + kSetupGroup - 1) / kSetupGroup;
   const uint64_t nagg = total / kAggStride + 2ull * T + 2;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -95,11 +111,15 @@ inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_o
   L->pub.header = take((uint64_t)T * sizeof(alias_ws_header));
   L->tile_start = take((T + 1ull) * 8);
   L->sec_start = take((T + 1ull) * 8);
+  L->grp_start = take((T + 1ull) * 8);
   L->flags = take(64);
-  L->grp = take(groups * 16 + 16);
+  L->sscr = take(sblocks * 24 + 24);
   L->tilew = take(tiles * sizeof(ReducePart));
+  L->grpw = take(grps * sizeof(ReducePart));
   L->tilesum = take(tiles * sizeof(TileSum));
   L->tilepre = take(tiles * sizeof(TilePrefix));
+  L->grpsum = take(grps * sizeof(TilePrefix));
+  L->grppre = take(grps * sizeof(TilePrefix));
   L->pub.l_idx = take(total * 4);
   L->pub.h_idx = take(total * 4);
   L->pub.l_w = take(total * 8);
@@ -116,6 +136,7 @@ inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_o
   L->pub.reduce_blocks = L->pub.tiles;
   L->tiles_max = tiles;
   L->secs_max = secs;
+  L->groups_max = grps;
   L->total = total;
   L->T = T;
   L->chunk = chunk;
@@ -141,5 +162,32 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 __device__ __forceinline__ dd load_dd(const dd *p) { return *p; }
+
+// largest t in [0, T) with start[t] <= x (start nondecreasing, start[T] > x)
+__device__ __forceinline__ uint32_t find_table(const uint64_t *start, uint32_t T, uint64_t x) {
+  uint32_t lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (start[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// the same over boundary indices: table t's boundaries start at sec_start[t] + t
+__device__ __forceinline__ uint32_t find_table_bnd(const uint64_t *sec, uint32_t T, uint64_t x) {
+  uint32_t lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sec[mid] + mid <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 
 }  // namespace amdalias

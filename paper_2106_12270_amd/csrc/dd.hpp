@@ -93,10 +93,12 @@ __device__ __forceinline__ double quot(dd a, dd b) {
   return q1 + q2;
 }
 
-// Divisor prepared once for many quotients: its dd value and the reciprocal
-// of its high part.
+// Divisor prepared once for many quotients: its dd value, the correctly
+// rounded reciprocal of its high part, and whether that reciprocal may be
+// used (no overflow or underflow near it).
 struct Divisor {
   double hi, lo, inv;
+  bool mk;
 };
 
 __device__ __forceinline__ Divisor make_divisor(dd b) {
@@ -104,16 +106,26 @@ __device__ __forceinline__ Divisor make_divisor(dd b) {
   d.hi = b.hi;
   d.lo = b.lo;
   d.inv = 1.0 / b.hi;
+  d.mk = b.hi >= 0x1p-1000 && b.hi <= 0x1p+1000;
   return d;
 }
 
-// a / b rounded to one binary64 with one IEEE division: q1 = a.hi / b.hi,
-// exact remainder of that division (the remainder of a correctly rounded
-// quotient is representable), corrected by a.lo and b.lo, times 1/b.hi.
-// Equals quot() whenever a and b are plain doubles whose quotient is not a
-// rounding midpoint, and differs from it by at most one unit in the last
-// place otherwise.
+// a / b rounded to one binary64 without a division.  Markstein's correction
+// (P. Markstein, IBM J. Res. Dev. 34(1), 1990): with y = RN(1/b) and
+// q0 = RN(a * y), within one ulp of a/b, the remainder r = a - b*q0 is exact
+// (one fma) and RN(q0 + r*y) is the correctly rounded a/b.  The low parts of
+// a and b enter the remainder as first-order terms.  So the result is the
+// correctly rounded quotient whenever a and b are plain doubles, and within
+// one unit in the last place of the dd quotient otherwise.  Outside the range
+// where the theorem's no-underflow assumption holds, an IEEE division step
+// with the same remainder correction is used.
 __device__ __forceinline__ double quot_fast(dd a, const Divisor &b) {
+  if (b.mk && (a.hi == 0.0 || fabs(a.hi) >= 0x1p-900)) {
+    const double q0 = a.hi * b.inv;
+    const double r = __fma_rn(-b.hi, q0, a.hi);
+    const double e = (r + a.lo) - b.lo * q0;
+    return __fma_rn(e, b.inv, q0);
+  }
   const double q1 = a.hi / b.hi;
   const dd p = two_prod(b.hi, q1);
   const double e = (((a.hi - p.hi) - p.lo) + a.lo) - b.lo * q1;
@@ -161,6 +173,17 @@ __device__ __forceinline__ dd wave_sum(dd v) {
     dd o = shfl_xor(v, m);
     // combine in lane order so both partners compute the identical sum
     v = ((__lane_id() & m) == 0) ? (v + o) : (o + v);
+  }
+  return v;
+}
+
+// wave_sum for terms of one sign (all partial sums then have that sign, and
+// the same-sign addition add_fast keeps the full dd accuracy).
+__device__ __forceinline__ dd wave_sum_fast(dd v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    dd o = shfl_xor(v, m);
+    v = ((__lane_id() & m) == 0) ? add_fast(v, o) : add_fast(o, v);
   }
   return v;
 }

@@ -24,6 +24,14 @@ constexpr int kLearnThreads = 256;
 constexpr int kMlpBatch = 128;
 constexpr uint32_t kMaxPwlSegments = 1u << 16;
 
+// The points of a gradient evaluation are split into `blocks` contiguous
+// ranges of ceil(points / blocks) (one per block of the multi-block kernel);
+// the gradient is the sum of the range partials in range order over points.
+__host__ __device__ inline uint32_t grad_blocks(uint32_t points) {
+  const uint32_t b = (points + 4095) / 4096;
+  return b > 256 ? 256 : b;
+}
+
 struct TrainLayout {
   uint64_t x, t, q, grad, m, v, part, loss_part, misc, total;
   uint32_t points, nparams, blocks;
@@ -41,8 +49,7 @@ inline bool train_layout(uint32_t kind, uint32_t segments, uint64_t points, Trai
   }
   if (points < 1 || points > (1ull << 31)) return false;
   const uint32_t np = model_nparams(kind, segments);
-  uint32_t blocks = (uint32_t)((points + 4095) / 4096);
-  if (blocks > 256) blocks = 256;
+  const uint32_t blocks = grad_blocks((uint32_t)points);
   uint64_t off = 0;
   auto take = [&](uint64_t b) {
     uint64_t at = off;
@@ -84,6 +91,23 @@ __global__ void k_targets(const alias_ws_header *hdr, const uint32_t *__restrict
 // ---------------------------------------------------------------------------
 // model initialisation: PWL = identity, MLP = small deterministic values
 // ---------------------------------------------------------------------------
+// Initial MLP parameter e: small deterministic values from Philox.
+__device__ __forceinline__ float mlp_init_value(uint32_t e) {
+  u32x4 c;
+  c.x = e;
+  c.y = 0x5EEDu;
+  c.z = 0u;
+  c.w = 0u;
+  const u32x4 r = philox4x32_10(c, 0x1234567u, 0x89ABCDEu);
+  const float u = ((float)(r.x >> 8) * (1.0f / 16777216.0f)) * 2.0f - 1.0f;  // [-1, 1)
+  if (e < 32) return 3.0f * u;                 // W1: spread the first-layer slopes
+  if (e < 64) return 1.5f * u;                 // b1
+  if (e < 64 + 1024) return u * 0.35f;         // W2
+  if (e < 64 + 1024 + 32) return 0.1f * u;     // b2
+  if (e < 64 + 1024 + 64) return 0.1f * u;     // W3
+  return 0.5f;                                 // b3: the middle of the target range
+}
+
 __global__ void k_init_model(SplitModel *M, uint32_t kind, uint32_t segments, float *m, float *v) {
   const uint32_t np = model_nparams(kind, segments);
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,31 +120,7 @@ __global__ void k_init_model(SplitModel *M, uint32_t kind, uint32_t segments, fl
   if (e >= np) return;
   m[e] = 0.0f;
   v[e] = 0.0f;
-  if (kind == kModelPWL) {
-    M->params[e] = (float)e / (float)segments;
-    return;
-  }
-  u32x4 c;
-  c.x = e;
-  c.y = 0x5EEDu;
-  c.z = 0u;
-  c.w = 0u;
-  const u32x4 r = philox4x32_10(c, 0x1234567u, 0x89ABCDEu);
-  const float u = ((float)(r.x >> 8) * (1.0f / 16777216.0f)) * 2.0f - 1.0f;  // [-1, 1)
-  float val;
-  if (e < 32)
-    val = 3.0f * u;  // W1: spread the first-layer slopes
-  else if (e < 64)
-    val = 1.5f * u;  // b1
-  else if (e < 64 + 1024)
-    val = u * 0.35f;  // W2
-  else if (e < 64 + 1024 + 32)
-    val = 0.1f * u;  // b2
-  else if (e < 64 + 1024 + 64)
-    val = 0.1f * u;  // W3
-  else
-    val = 0.5f;  // b3: the middle of the target range
-  M->params[e] = val;
+  M->params[e] = (kind == kModelPWL) ? (float)e / (float)segments : mlp_init_value(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,80 +222,95 @@ struct MlpShared {
   double red[kLearnThreads / 64];
 };
 
+// One batch of up to kMlpBatch points [base, base + cnt): thread pi runs
+// point base + pi forward and backward into LDS and adds its squared error
+// to *lacc.  P: the parameters (global or LDS).
+__device__ __forceinline__ void mlp_batch_fwd_bwd(const float *P, const float *__restrict__ x,
+                                                  const float *__restrict__ t, uint32_t base,
+                                                  uint32_t cnt, MlpShared &S, double *lacc) {
+  const float *W1 = P, *b1 = P + 32, *W2 = P + 64, *b2 = P + 64 + 1024, *W3 = P + 64 + 1024 + 32;
+  const float b3 = P[64 + 1024 + 64];
+  if (threadIdx.x < cnt) {
+    const int pi = threadIdx.x;
+    const float xi = x[base + pi];
+    float h1[kMlpHidden];
+#pragma unroll
+    for (int a = 0; a < kMlpHidden; ++a) {
+      h1[a] = tanhf(W1[a] * xi + b1[a]);
+      S.h1[pi][a] = h1[a];
+    }
+    float y = b3;
+    float h2[kMlpHidden];
+    for (int b = 0; b < kMlpHidden; ++b) {
+      float z = b2[b];
+#pragma unroll
+      for (int a = 0; a < kMlpHidden; ++a) z += W2[b * kMlpHidden + a] * h1[a];
+      h2[b] = tanhf(z);
+      S.h2[pi][b] = h2[b];
+      y += W3[b] * h2[b];
+    }
+    const float r = y - t[base + pi];
+    *lacc += (double)r * (double)r;
+    const float dy = 2.0f * r;
+    S.dy[pi] = dy;
+    S.x[pi] = xi;
+    float dz2[kMlpHidden];
+#pragma unroll
+    for (int b = 0; b < kMlpHidden; ++b) {
+      dz2[b] = dy * W3[b] * (1.0f - h2[b] * h2[b]);
+      S.dz2[pi][b] = dz2[b];
+    }
+    for (int a = 0; a < kMlpHidden; ++a) {
+      float dh1 = 0.0f;
+#pragma unroll
+      for (int b = 0; b < kMlpHidden; ++b) dh1 += W2[b * kMlpHidden + a] * dz2[b];
+      S.dz1[pi][a] = dh1 * (1.0f - h1[a] * h1[a]);
+    }
+  }
+}
+
+// Adds the batch's gradient contributions to the parameters this thread owns
+// (e = threadIdx.x + r * kLearnThreads), summing the points in order.
+__device__ __forceinline__ void mlp_batch_accumulate(const MlpShared &S, uint32_t cnt,
+                                                     double acc[5]) {
+#pragma unroll
+  for (int r = 0; r < 5; ++r) {
+    const int e = threadIdx.x + r * kLearnThreads;
+    if (e >= kMlpParams) break;
+    double sacc = 0.0;
+    for (uint32_t pi = 0; pi < cnt; ++pi) {
+      float g;
+      if (e < 32)
+        g = S.dz1[pi][e] * S.x[pi];
+      else if (e < 64)
+        g = S.dz1[pi][e - 32];
+      else if (e < 64 + 1024)
+        g = S.dz2[pi][(e - 64) >> 5] * S.h1[pi][(e - 64) & 31];
+      else if (e < 64 + 1024 + 32)
+        g = S.dz2[pi][e - 64 - 1024];
+      else if (e < 64 + 1024 + 64)
+        g = S.dy[pi] * S.h2[pi][e - 64 - 1024 - 32];
+      else
+        g = S.dy[pi];
+      sacc += (double)g;
+    }
+    acc[r] += sacc;
+  }
+}
+
 __global__ __launch_bounds__(kLearnThreads) void k_mlp_grad_partial(
     const SplitModel *M, const float *__restrict__ x, const float *__restrict__ t, uint32_t points,
     double *__restrict__ part, double *__restrict__ loss_part) {
   __shared__ MlpShared S;
-  const float *P = M->params;
-  const float *W1 = P, *b1 = P + 32, *W2 = P + 64, *b2 = P + 64 + 1024, *W3 = P + 64 + 1024 + 32;
-  const float b3 = P[64 + 1024 + 64];
   const uint32_t per = (points + gridDim.x - 1) / gridDim.x;
   const uint32_t b0 = blockIdx.x * per, e0 = (b0 + per < points) ? b0 + per : points;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double lacc = 0.0;
   for (uint32_t base = b0; base < e0; base += kMlpBatch) {
     const uint32_t cnt = (e0 - base < (uint32_t)kMlpBatch) ? e0 - base : (uint32_t)kMlpBatch;
-    if (threadIdx.x < cnt) {
-      const int pi = threadIdx.x;
-      const float xi = x[base + pi];
-      float h1[kMlpHidden];
-#pragma unroll
-      for (int a = 0; a < kMlpHidden; ++a) {
-        h1[a] = tanhf(W1[a] * xi + b1[a]);
-        S.h1[pi][a] = h1[a];
-      }
-      float y = b3;
-      float h2[kMlpHidden];
-      for (int b = 0; b < kMlpHidden; ++b) {
-        float z = b2[b];
-#pragma unroll
-        for (int a = 0; a < kMlpHidden; ++a) z += W2[b * kMlpHidden + a] * h1[a];
-        h2[b] = tanhf(z);
-        S.h2[pi][b] = h2[b];
-        y += W3[b] * h2[b];
-      }
-      const float r = y - t[base + pi];
-      lacc += (double)r * (double)r;
-      const float dy = 2.0f * r;
-      S.dy[pi] = dy;
-      S.x[pi] = xi;
-      float dz2[kMlpHidden];
-#pragma unroll
-      for (int b = 0; b < kMlpHidden; ++b) {
-        dz2[b] = dy * W3[b] * (1.0f - h2[b] * h2[b]);
-        S.dz2[pi][b] = dz2[b];
-      }
-      for (int a = 0; a < kMlpHidden; ++a) {
-        float dh1 = 0.0f;
-#pragma unroll
-        for (int b = 0; b < kMlpHidden; ++b) dh1 += W2[b * kMlpHidden + a] * dz2[b];
-        S.dz1[pi][a] = dh1 * (1.0f - h1[a] * h1[a]);
-      }
-    }
+    mlp_batch_fwd_bwd(M->params, x, t, base, cnt, S, &lacc);
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-      const int e = threadIdx.x + r * kLearnThreads;
-      if (e >= kMlpParams) break;
-      double sacc = 0.0;
-      for (uint32_t pi = 0; pi < cnt; ++pi) {
-        float g;
-        if (e < 32)
-          g = S.dz1[pi][e] * S.x[pi];
-        else if (e < 64)
-          g = S.dz1[pi][e - 32];
-        else if (e < 64 + 1024)
-          g = S.dz2[pi][(e - 64) >> 5] * S.h1[pi][(e - 64) & 31];
-        else if (e < 64 + 1024 + 32)
-          g = S.dz2[pi][e - 64 - 1024];
-        else if (e < 64 + 1024 + 64)
-          g = S.dy[pi] * S.h2[pi][e - 64 - 1024 - 32];
-        else
-          g = S.dy[pi];
-        sacc += (double)g;
-      }
-      acc[r] += sacc;
-    }
+    mlp_batch_accumulate(S, cnt, acc);
     __syncthreads();
   }
 #pragma unroll
@@ -328,16 +343,27 @@ __global__ void k_loss_final(const double *__restrict__ loss_part, uint32_t bloc
 // ---------------------------------------------------------------------------
 // Adam (Kingma & Ba) with bias correction factors computed on the host
 // ---------------------------------------------------------------------------
+// Step size of epoch e: lr decayed by a cosine from 1 to 0.02 over the fit.
+__device__ __forceinline__ float cosine_lr(float lr, uint32_t e, uint32_t epochs) {
+  const double c = 0.5 * (1.0 + cos(3.141592653589793 * (double)e / (double)epochs));
+  return (float)((double)lr * (0.02 + 0.98 * c));
+}
+
+__device__ __forceinline__ void adam_update(float &p, float g, float &mo, float &ve, float lr,
+                                            float bc1, float bc2) {
+  const float m = 0.9f * mo + 0.1f * g;
+  const float v = 0.999f * ve + 0.001f * g * g;
+  mo = m;
+  ve = v;
+  p -= lr * (m / bc1) / (sqrtf(v / bc2) + 1e-12f);
+}
+
 __global__ void k_adam(SplitModel *M, const double *__restrict__ grad, float *__restrict__ mo,
-                       float *__restrict__ ve, uint32_t np, float lr, float bc1, float bc2) {
+                       float *__restrict__ ve, uint32_t np, float lr, uint32_t epoch,
+                       uint32_t epochs, float bc1, float bc2) {
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= np) return;
-  const float g = (float)grad[e];
-  const float m = 0.9f * mo[e] + 0.1f * g;
-  const float v = 0.999f * ve[e] + 0.001f * g * g;
-  mo[e] = m;
-  ve[e] = v;
-  M->params[e] -= lr * (m / bc1) / (sqrtf(v / bc2) + 1e-12f);
+  adam_update(M->params[e], (float)grad[e], mo[e], ve[e], cosine_lr(lr, epoch, epochs), bc1, bc2);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,6 +421,159 @@ static int launch_grad(uint32_t kind, const SplitModel *M, const float *x, const
     if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, lpart, T.blocks, points, loss);
   }
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// Batched fit: one MLP per table of a finished batched build.  Training
+// points live in the boundary index space of the build (table t's points are
+// its boundaries sec_start[t] + t ...).  One workgroup trains one table for
+// all epochs without leaving the kernel.  Its arithmetic is that of the
+// single-table fit step for step (same batches, same range partials summed
+// in the same order, same Adam update and step sizes), so each table's model
+// is bit for bit the model alias_split_model_fit would train on that table
+// alone.
+// ---------------------------------------------------------------------------
+struct BatchTrainLayout {
+  uint64_t x, t, q, m, v, total;
+};
+
+inline bool batch_train_layout(const Layout &L, BatchTrainLayout *B) {
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) {
+    uint64_t at = off;
+    off = align256(off + b);
+    return at;
+  };
+  B->x = take(L.secs_max * 4);
+  B->t = take(L.secs_max * 4);
+  B->q = take(L.secs_max * 4);
+  B->m = take((uint64_t)L.T * kMlpParams * 4);
+  B->v = take((uint64_t)L.T * kMlpParams * 4);
+  B->total = off;
+  return true;
+}
+
+__global__ void k_targets_batched(const alias_ws_header *hdr, const uint64_t *__restrict__ offsets,
+                                  const uint64_t *__restrict__ sec_start,
+                                  const uint32_t *__restrict__ split_j, uint32_t T, uint32_t chunk,
+                                  float *__restrict__ x, float *__restrict__ t,
+                                  int32_t *__restrict__ q) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= sec_start[T] + T) return;
+  const uint32_t tb = find_table_bnd(sec_start, T, b);
+  if (hdr[tb].status != ALIAS_OK) return;
+  const uint64_t n = offsets[tb + 1] - offsets[tb];
+  const uint64_t k = b - (sec_start[tb] + tb);
+  const uint64_t m = (k * chunk < n) ? k * chunk : n;
+  const uint64_t H = hdr[tb].H;
+  const uint32_t j = split_j[b];
+  x[b] = (float)((double)m / (double)n);
+  t[b] = H ? (float)((double)j / (double)H) : 0.0f;
+  q[b] = (int32_t)(j / kAggStride);
+}
+
+struct FitShared {
+  MlpShared S;
+  float P[kMlpParams + 3];
+  int32_t err[kLearnThreads / 64];
+};
+
+__global__ __launch_bounds__(kLearnThreads) void k_fit_mlp_batched(
+    const alias_ws_header *hdr, const uint64_t *__restrict__ offsets,
+    const uint64_t *__restrict__ sec_start, const float *__restrict__ xs,
+    const float *__restrict__ ts, const int32_t *__restrict__ qs, uint32_t chunk,
+    unsigned char *models, uint64_t stride, float *mo_all, float *ve_all, uint32_t epochs,
+    float lr, double *loss_out) {
+  __shared__ FitShared F;
+  const uint32_t tb = blockIdx.x;
+  const int tid = threadIdx.x;
+  SplitModel *M = (SplitModel *)(models + (uint64_t)tb * stride);
+  if (hdr[tb].status != ALIAS_OK) {  // no training data: a model the split never trusts
+    if (tid == 0) {
+      M->kind = kModelMLP;
+      M->segments = 0;
+      M->eps_q = -1;
+      M->nparams = kMlpParams;
+      if (loss_out) loss_out[tb] = __builtin_nan("");
+    }
+    return;
+  }
+  const uint64_t pb = sec_start[tb] + tb;
+  const uint32_t npts = (uint32_t)(sec_start[tb + 1] - sec_start[tb] + 1);
+  const float *x = xs + pb, *t = ts + pb;
+  const int32_t *q = qs + pb;
+  float *mo = mo_all + (uint64_t)tb * kMlpParams, *ve = ve_all + (uint64_t)tb * kMlpParams;
+  for (int e = tid; e < kMlpParams; e += kLearnThreads) {
+    F.P[e] = mlp_init_value(e);
+    mo[e] = 0.0f;
+    ve[e] = 0.0f;
+  }
+  __syncthreads();
+  const uint32_t blocks = grad_blocks(npts);
+  const uint32_t per = (npts + blocks - 1) / blocks;
+  double p1 = 1.0, p2 = 1.0;
+  const uint32_t passes = epochs ? epochs : 1;  // epochs == 0: the loss at the start
+  for (uint32_t ep = 0; ep < passes; ++ep) {
+    const bool last = ep + 1 == passes;
+    double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double lsum = 0.0;
+    for (uint32_t b = 0; b < blocks; ++b) {
+      const uint32_t b0 = b * per, e0 = (b0 + per < npts) ? b0 + per : npts;
+      double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      double lacc = 0.0;
+      for (uint32_t base = b0; base < e0; base += kMlpBatch) {
+        const uint32_t cnt = (e0 - base < (uint32_t)kMlpBatch) ? e0 - base : (uint32_t)kMlpBatch;
+        mlp_batch_fwd_bwd(F.P, x, t, base, cnt, F.S, &lacc);
+        __syncthreads();
+        mlp_batch_accumulate(F.S, cnt, acc);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 5; ++r) tot[r] += acc[r];
+      if (last) lsum += block_sum_f64(lacc, F.S.red);
+    }
+    if (last && tid == 0 && loss_out) loss_out[tb] = lsum / (double)npts;
+    if (epochs == 0) break;
+    p1 *= 0.9;
+    p2 *= 0.999;
+    const float bc1 = (float)(1.0 - p1), bc2 = (float)(1.0 - p2);
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      const int e = tid + r * kLearnThreads;
+      if (e < kMlpParams) {
+        const float g = (float)(tot[r] / (double)npts);
+        adam_update(F.P[e], g, mo[e], ve[e], cosine_lr(lr, ep, epochs), bc1, bc2);
+      }
+    }
+    __syncthreads();
+  }
+  // the trained parameters, then the bracket half-width over the points
+  for (int e = tid; e < kMlpParams; e += kLearnThreads) M->params[e] = F.P[e];
+  const uint64_t n = offsets[tb + 1] - offsets[tb];
+  const uint64_t H = hdr[tb].H;
+  int32_t err = 0;
+  for (uint32_t k = tid; k < npts; k += kLearnThreads) {
+    const uint64_t m = ((uint64_t)k * chunk < n) ? (uint64_t)k * chunk : n;
+    int64_t d = predict_q(F.P, kModelMLP, 0, m, n, H) - (int64_t)q[k];
+    if (d < 0) d = -d;
+    const int32_t dd32 = d > 0x3ffffff ? 0x3ffffff : (int32_t)d;
+    err = dd32 > err ? dd32 : err;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int32_t o = __shfl_xor(err, m, 64);
+    err = o > err ? o : err;
+  }
+  if ((tid & 63) == 0) F.err[tid >> 6] = err;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t e = F.err[0];
+    for (int w = 1; w < kLearnThreads / 64; ++w) e = F.err[w] > e ? F.err[w] : e;
+    M->kind = kModelMLP;
+    M->segments = 0;
+    M->eps_q = e + 1;
+    M->nparams = kMlpParams;
+  }
 }
 
 int launch_split_only(void *d_ws, const uint64_t *d_offsets, uint64_t n1, const Layout &Lo,
@@ -461,10 +640,8 @@ int alias_split_model_fit(const void *d_build_ws, uint64_t n, const alias_build_
     if (rc) return rc;
     p1 *= b1;
     p2 *= b2;
-    const double cosf_ = 0.5 * (1.0 + cos(3.141592653589793 * (double)e / (double)epochs));
-    const float lre = (float)(lr * (0.02 + 0.98 * cosf_));
-    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, M, grad, mo, ve, np, lre,
-                       (float)(1.0 - p1), (float)(1.0 - p2));
+    hipLaunchKernelGGL(k_adam, dim3((np + 255) / 256), dim3(256), 0, st, M, grad, mo, ve, np, lr, e,
+                       epochs, (float)(1.0 - p1), (float)(1.0 - p2));
   }
   if (epochs == 0) {
     int rc = launch_grad(kind, M, x, t, points, T, tw, grad, loss, st);
@@ -488,6 +665,51 @@ int alias_split_model_grad(uint32_t kind, uint32_t segments, const void *d_model
   if (train_ws_bytes < T.total || ((uintptr_t)d_train_ws & 255)) return ALIAS_EWORKSPACE;
   return launch_grad(kind, (const SplitModel *)d_model, d_x, d_t, (uint32_t)points, T,
                      (char *)d_train_ws, d_grad, d_loss, (hipStream_t)stream);
+}
+
+size_t alias_split_model_fit_batched_workspace_bytes(uint32_t T, uint64_t total_items,
+                                                     const alias_build_opts *build_opts,
+                                                     uint32_t kind) {
+  Layout L;
+  BatchTrainLayout B;
+  if (kind != ALIAS_MODEL_MLP) return 0;
+  if (!compute_layout_batch(T, total_items, build_opts, &L)) return 0;
+  batch_train_layout(L, &B);
+  return (size_t)B.total;
+}
+
+int alias_split_model_fit_batched(const void *d_build_ws, const uint64_t *d_offsets, uint32_t T,
+                                  uint64_t total_items, const alias_build_opts *build_opts,
+                                  uint32_t kind, uint32_t epochs, float lr, void *d_models,
+                                  size_t model_stride, void *d_train_ws, size_t train_ws_bytes,
+                                  double *d_loss, void *stream) {
+  Layout L;
+  BatchTrainLayout B;
+  if (kind != ALIAS_MODEL_MLP) return ALIAS_EINVAL;
+  if (!d_build_ws || !d_offsets || !d_models || !d_train_ws) return ALIAS_EINVAL;
+  if (((uintptr_t)d_build_ws & 255) || ((uintptr_t)d_offsets & 7) || ((uintptr_t)d_models & 3) ||
+      ((uintptr_t)d_train_ws & 255) || ((uintptr_t)d_loss & 7))
+    return ALIAS_EINVAL;
+  if (!compute_layout_batch(T, total_items, build_opts, &L)) return ALIAS_EINVAL;
+  if (model_stride < alias_split_model_bytes(ALIAS_MODEL_MLP, 0) || (model_stride & 3))
+    return ALIAS_EINVAL;
+  if (!(lr > 0.0f) || epochs > 1000000) return ALIAS_EINVAL;
+  batch_train_layout(L, &B);
+  if (train_ws_bytes < B.total) return ALIAS_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const char *bw = (const char *)d_build_ws;
+  char *tw = (char *)d_train_ws;
+  const alias_ws_header *hdr = (const alias_ws_header *)(bw + L.pub.header);
+  const uint64_t *sec_start = (const uint64_t *)(bw + L.sec_start);
+  const uint32_t *split_j = (const uint32_t *)(bw + L.pub.split_j);
+  float *x = (float *)(tw + B.x), *t = (float *)(tw + B.t);
+  int32_t *q = (int32_t *)(tw + B.q);
+  hipLaunchKernelGGL(k_targets_batched, dim3((uint32_t)((L.secs_max + 255) / 256)), dim3(256), 0,
+                     st, hdr, d_offsets, sec_start, split_j, T, L.chunk, x, t, q);
+  hipLaunchKernelGGL(k_fit_mlp_batched, dim3(T), dim3(kLearnThreads), 0, st, hdr, d_offsets,
+                     sec_start, x, t, q, L.chunk, (unsigned char *)d_models, (uint64_t)model_stride,
+                     (float *)(tw + B.m), (float *)(tw + B.v), epochs, lr, d_loss);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 
 int alias_resplit(void *d_ws, uint64_t n, const alias_build_opts *opts, void *stream) {

@@ -63,14 +63,19 @@ __device__ __forceinline__ float pwl_forward(const float *p, uint32_t K, float x
   return p[s] + f * (p[s + 1] - p[s]);
 }
 
-// Predicted aggregate index q = floor(j_hat / 64) for the boundary after m rows.
-__device__ __forceinline__ int64_t learned_predict_q(const SplitModel *M, uint64_t m, uint64_t n,
-                                                     uint64_t H) {
+// Predicted aggregate index q = floor(j_hat / 64) for the boundary after m
+// rows, from the parameters P of a model of the given kind.
+__device__ __forceinline__ int64_t predict_q(const float *P, uint32_t kind, uint32_t segments,
+                                             uint64_t m, uint64_t n, uint64_t H) {
   const float x = (float)((double)m / (double)n);
-  const float y = (M->kind == kModelPWL) ? pwl_forward(M->params, M->segments, x)
-                                         : mlp_forward(M->params, x);
+  const float y = (kind == kModelPWL) ? pwl_forward(P, segments, x) : mlp_forward(P, x);
   const double jhat = (double)y * (double)H;
   return (int64_t)floor(jhat / 64.0);
+}
+
+__device__ __forceinline__ int64_t learned_predict_q(const SplitModel *M, uint64_t m, uint64_t n,
+                                                     uint64_t H) {
+  return predict_q(M->params, M->kind, M->segments, m, n, H);
 }
 
 }  // namespace amdalias

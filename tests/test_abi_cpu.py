@@ -190,3 +190,39 @@ def test_product_package_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "alias_oracle" not in text, f
+
+
+def test_tuner_host_logic_and_argument_checks():
+    from paper_2106_12270_amd import tune
+
+    tune._register()
+    L = pkg.lib()
+    o = pkg.BuildOpts()
+    ch = (C.c_uint32 * 3)(256, 1024, 100)  # 100 is not a valid chunk: skipped
+    b = L.alias_tune_workspace_bytes(10, 50000, C.byref(o), ch, 3)
+    assert b == max(L.alias_build_batched_workspace_bytes(10, 50000, C.byref(pkg._opts(c)))
+                    for c in (256, 1024))
+    assert L.alias_tune_workspace_bytes(10, 50000, C.byref(o), ch, 0) == 0
+    fake = C.c_void_p(0x10000)
+    wv = (C.c_uint32 * 1)(4)
+    times = (C.c_float * 3)()
+    best = pkg.BuildOpts()
+    tb = L.alias_tune_build
+    # bad arguments are rejected before any device work
+    assert tb(fake, fake, 10, 50000, fake, fake, b, fake, C.byref(o), None, 3, wv, 1, 2, times,
+              C.byref(best), None) == pkg.ALIAS_EINVAL
+    assert tb(fake, fake, 10, 50000, fake, fake, b, fake, C.byref(o), ch, 3, wv, 1, 0, times,
+              C.byref(best), None) == pkg.ALIAS_EINVAL
+    assert tb(fake, fake, 10, 50000, C.c_void_p(0x10008), fake, b, fake, C.byref(o), ch, 3, wv,
+              1, 2, times, C.byref(best), None) == pkg.ALIAS_EINVAL
+    assert tb(fake, fake, 10, 50000, fake, fake, b, fake, C.byref(o), ch, 3, wv, 1, 2, None,
+              C.byref(best), None) == pkg.ALIAS_EINVAL
+
+
+def test_tune_cache_key_is_shape_based():
+    from paper_2106_12270_amd import tune
+
+    k1 = tune.workload_key("gfx950", 1024, 750_000_000, 16384, 4194304)
+    k2 = tune.workload_key("gfx950", 1024, 760_000_000, 16500, 4_200_000)
+    k3 = tune.workload_key("gfx950", 100_000, 787_000_000, 16, 65536)
+    assert k1 == k2 and k1 != k3

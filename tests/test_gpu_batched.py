@@ -319,3 +319,94 @@ def test_full_size_batches_sampled_tables(name):
         k = min(de - ds, 200_000)
         ref = oracle.sample(p, a, k, seed, first=0, table=t)
         assert np.array_equal(out[ds:ds + k].cpu().numpy().view(np.uint32), ref), t
+
+
+def test_batched_mlp_fit_equals_single_table_fits():
+    """One launch trains a model per table; each equals the single-table fit
+    bit for bit (the single-table gradients are pinned to the CPU oracle),
+    including a table with more than 4096 training boundaries and a table
+    whose build failed."""
+    sizes = [300_000, 5000, 1, 64, 70_000, 1000]
+    w = inputs.batch_lognormal(sizes, seed=41, sigma=2.0)
+    off = inputs.offsets_from_sizes(sizes)
+    w[int(off[5]) + 3] = float("nan")  # table 5 fails
+    chunk, epochs = 64, 40
+    say("batched fit", sizes)
+    bb, st, p0, a0 = batched_build(w, off, chunk)
+    assert list(st) == [0, 0, 0, 0, 0, pkg.ALIAS_EWEIGHTS]
+    od = dev_u64(off)
+    models, loss = bb.fit_split_models(od, epochs=epochs, lr=0.02)
+    torch.cuda.synchronize()
+    S = pkg.BatchBuilder.MODEL_STRIDE
+    for t in range(5):
+        s, e = int(off[t]), int(off[t + 1])
+        b = pkg.Builder(e - s, chunk, device=DEV)
+        b.build(torch.from_numpy(w[s:e]).to(DEV))
+        m, l1 = b.fit_split_model("mlp", 0, epochs, lr=0.02)
+        torch.cuda.synchronize()
+        got = models[t * S:t * S + m.numel()]
+        assert torch.equal(got, m), t
+        assert float(loss[t].item()) == float(l1.item()), t
+    kind, seg, eps, npar = pkg.model_header(models[5 * S:5 * S + 16])
+    assert eps == -1 and np.isnan(float(loss[5].item()))
+    # the learned batched build with these models: same tables, no fallbacks
+    ok = np.array([0, 1, 2, 3, 4])
+    w2 = w.copy()
+    w2[int(off[5]) + 3] = 1.0
+    _, _, p1, a1 = batched_build(w2, off, chunk)
+    bb2 = pkg.BatchBuilder(len(sizes), len(w), chunk, split="learned", model=models,
+                           model_stride=S, device=DEV)
+    wd = torch.from_numpy(w2).to(DEV)
+    pr, al = bb2.build(wd, od)
+    torch.cuda.synchronize()
+    assert (bb2.status == 0).all()
+    assert np.array_equal(pr.cpu().numpy(), p1)
+    assert np.array_equal(al.cpu().numpy().view(np.uint32), a1)
+    h = bb2.headers()
+    assert all(h[t].split_fallbacks == 0 for t in ok)
+
+
+def test_autotuner_picks_a_valid_shape_and_caches_it(tmp_path, monkeypatch):
+    from paper_2106_12270_amd import tune
+
+    monkeypatch.setenv("ALIAS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    sizes = inputs.log_uniform_sizes(400, 16, 1 << 16, seed=51)
+    w = inputs.batch_lognormal(sizes, seed=52)
+    off = inputs.offsets_from_sizes(sizes)
+    say("autotune", len(sizes), len(w))
+    wd = torch.from_numpy(w).to(DEV)
+    od = dev_u64(off)
+    res = tune.tune(wd, od, int(sizes.min()), int(sizes.max()), reps=2)
+    torch.cuda.synchronize()
+    assert not res["cached"] and res["chunk"] in tune.CHUNKS and res["pack_waves"] in tune.WAVES
+    assert res["times"][f"{res['chunk']}x{res['pack_waves']}"] == res["ms"]
+    assert "2048x1" not in res["times"]  # invalid shapes are skipped, not timed
+    again = tune.tune(wd, od, int(sizes.min()), int(sizes.max()))
+    assert again["cached"] and again["chunk"] == res["chunk"]
+    # the tuned options build the same tables (aliases exact, invariant)
+    bb, st, p, a = batched_build(w, off, res["chunk"], pack_waves=res["pack_waves"])
+    assert (st == 0).all()
+    for t in range(0, len(sizes), 37):
+        s, e = int(off[t]), int(off[t + 1])
+        op, oa = oracle.psa_build(w[s:e], chunk=res["chunk"])
+        assert np.array_equal(a[s:e], oa)
+        r = oracle.check(w[s:e], p[s:e], a[s:e])
+        assert r["max_rel"] <= 1e-12
+
+
+@pytest.mark.parametrize("chunk,waves", [(64, 1), (128, 1), (128, 2), (256, 1), (256, 2),
+                                         (512, 1), (512, 4), (1024, 2), (2048, 4)])
+def test_every_pack_shape_builds_the_oracle_table(chunk, waves):
+    """Exact inputs: every (chunk, waves-per-section) launch shape writes the
+    oracle's table bit for bit."""
+    sizes = [1, 5000, 3 * 4096 + 77, 70000]
+    parts = [inputs.exact_integers(n, seed=7 * n + chunk, zero_frac=0.05) for n in sizes]
+    w = np.concatenate(parts)
+    off = inputs.offsets_from_sizes(sizes)
+    say("pack shape", chunk, waves)
+    _, st, p, a = batched_build(w, off, chunk, pack_waves=waves)
+    assert (st == 0).all()
+    for t, wt in enumerate(parts):
+        s, e = int(off[t]), int(off[t + 1])
+        op, oa = oracle.psa_build(wt, chunk=chunk)
+        assert np.array_equal(a[s:e], oa) and np.array_equal(p[s:e], op), t

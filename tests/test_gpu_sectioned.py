@@ -1,0 +1,102 @@
+"""GPU parity of sectioned sampling (Sec. 5 sectioned methods, exact
+per-section counts) through the C ABI: output and per-section counts equal
+the CPU oracle's bit for bit, from both table layouts, across section sizes,
+ragged last sections, one-section and many-section tables, and at the full
+2^27-row workload size on sampled windows.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import paper_2106_12270_amd as pkg
+from paper_2106_12270_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pkg.lib()
+    oracle.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n,log2r,count", [(1, 6, 1000), (64, 6, 5000), (65, 6, 5001),
+                                           (5000, 7, 300_001), (100_000, 10, 1_000_000),
+                                           (100_000, 20, 77_777), ((1 << 18) + 3, 12, 2_000_000),
+                                           (70_000, 6, 0)])
+@pytest.mark.parametrize("rows", [False, True])
+def test_sectioned_bit_exact(n, log2r, count, rows):
+    w = inputs.power_law(n, 1.0, n + log2r) if n > 1 else np.array([1.5])
+    prob, alias = oracle.psa_build(w, chunk=1024)
+    seed, table = inputs.SAMPLE_SEED + n, 5
+    say("sectioned", n, log2r, count, rows)
+    ss = pkg.SectionedSampler(n, count, log2r, device=DEV)
+    counts = torch.zeros(ss.sections, dtype=torch.int64, device=DEV)
+    out = torch.full((max(count, 1),), -3, dtype=torch.int32, device=DEV)[:count]
+    if rows:
+        r = torch.zeros((n, 4), dtype=torch.int32, device=DEV)
+        r.view(torch.float64)[:, 0] = torch.from_numpy(prob).to(DEV)
+        r[:, 2] = torch.from_numpy(alias.view(np.int32)).to(DEV)
+        ss.sample_rows(r, seed, table, out=out, counts=counts)
+    else:
+        ss.sample(torch.from_numpy(prob).to(DEV), torch.from_numpy(alias.view(np.int32)).to(DEV),
+                  seed, table, out=out, counts=counts)
+    torch.cuda.synchronize()
+    ref, rc = oracle.sample_sectioned(prob, alias, count, seed, log2r, table=table)
+    assert np.array_equal(counts.cpu().numpy().view(np.uint64), rc)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+
+
+def test_sectioned_rejects_bad_arguments():
+    L = pkg.lib()
+    assert L.alias_sample_sectioned_workspace_bytes(0, 10, 10) == 0
+    assert L.alias_sample_sectioned_workspace_bytes(100, 10, 5) == 0
+    assert L.alias_sample_sectioned_workspace_bytes(100, 10, 32) == 0
+    assert L.alias_sample_sectioned_workspace_bytes((1 << 32) - 1, 10, 6) == 0  # > 2^20 sections
+
+
+def test_sectioned_full_size_windows():
+    """The 2^27-row power-law table and 10^9 draws in the benchmark's
+    configuration: the section counts equal the oracle's (all of them), and
+    the draws of sampled sections are bit-exact."""
+    name = "powerlaw_2p27"
+    cfg = inputs.WORKLOADS[name]
+    n, count, log2r = cfg["n"], cfg["draws"], 16
+    say("sectioned full", n, count)
+    w = inputs.make_weights(name)
+    b = pkg.Builder(n, cfg["chunk"], device=DEV)
+    rows = b.build_rows(torch.from_numpy(w).to(DEV))
+    ss = pkg.SectionedSampler(n, count, log2r, device=DEV)
+    counts = torch.zeros(ss.sections, dtype=torch.int64, device=DEV)
+    out = ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, counts=counts)
+    torch.cuda.synchronize()
+    assert int(b.status.item()) == 0
+    c = counts.cpu().numpy().view(np.uint64)
+    assert int(c.sum()) == count
+    # every section count against the oracle's
+    assert np.array_equal(c, oracle.sectioned_counts(n, count, inputs.SAMPLE_SEED, log2r))
+    prob, alias = pkg.rows_split(rows)
+    p = prob.cpu().numpy()
+    a = alias.cpu().numpy().view(np.uint32)
+    off = np.concatenate([[0], np.cumsum(c)]).astype(np.int64)
+    rng = np.random.default_rng(3)
+    for s in sorted(set(rng.integers(0, len(c), 4).tolist()) | {0, len(c) - 1}):
+        k = int(c[s])
+        got = out[off[s]:off[s] + k].cpu().numpy().view(np.uint32)
+        for j in sorted(set(rng.integers(0, k, 300).tolist()) | {0, k - 1}):
+            exp = oracle.sectioned_draw(p, a, inputs.SAMPLE_SEED, log2r, s, j)
+            assert int(got[j]) == exp, (s, j)
