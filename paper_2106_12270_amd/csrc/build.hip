@@ -579,17 +579,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_table(Batch B) {
 // ---------------------------------------------------------------------------
 // k_partition: stable partition of one tile with known offsets
 // ---------------------------------------------------------------------------
+// 512 threads x 8 items per tile: more waves per CU than 256 x 16 (the LDS
+// staging area bounds the blocks per CU), at a slightly higher scan cost
+constexpr int kPartThreads = 512;
+constexpr int kPartItems = kTileItems / kPartThreads;  // 8
+constexpr int kPartWaves = kPartThreads / 64;
+
 struct PartShared {
   double val[kTileItems + kTileItems / 16];  // staging (padded for the transpose)
   uint32_t idx[kTileItems];
-  dd wl[4], wh[4];
-  uint32_t cl[4], ch[4];
+  dd wl[kPartWaves], wh[kPartWaves];
+  uint32_t cl[kPartWaves], ch[kPartWaves];
   uint32_t t;
 };
 
 __device__ __forceinline__ int spos(int i) { return i + (i >> 4); }
 
-__global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
+__global__ __launch_bounds__(kPartThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_partition(Batch B) {
   __shared__ PartShared S;
   if (B.flags[0]) return;
   const uint64_t tile = blockIdx.x;
@@ -606,19 +612,19 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
 
   // 1. striped, coalesced load into the staging area
 #pragma unroll
-  for (int k = 0; k < kItemsPerThread; ++k) {
-    const int e = k * kTileThreads + tid;
+  for (int k = 0; k < kPartItems; ++k) {
+    const int e = k * kPartThreads + tid;
     const uint64_t li = lbase + e;
     S.val[spos(e)] = (li < n) ? B.w[off + li] : 0.0;
   }
   __syncthreads();
 
-  // 2. blocked view: this thread owns items tid*16 .. tid*16+15
-  double x[kItemsPerThread];
+  // 2. blocked view: this thread owns items tid*8 .. tid*8+7
+  double x[kPartItems];
   uint32_t lmask = 0, vmask = 0;
 #pragma unroll
-  for (int u = 0; u < kItemsPerThread; ++u) {
-    const int e = tid * kItemsPerThread + u;
+  for (int u = 0; u < kPartItems; ++u) {
+    const int e = tid * kPartItems + u;
     x[u] = S.val[spos(e)];
     const bool valid = lbase + e < n;
     const bool light = valid && le(dd_make(x[u], 0.0), avg);
@@ -656,7 +662,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
   __syncthreads();  // also: every thread has its x[] in registers
   uint32_t cl_off = 0, ch_off = 0, Lt = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kPartWaves; ++k) {
     if (k < wave) {
       cl_off += S.cl[k];
       ch_off += S.ch[k];
@@ -674,12 +680,12 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
   //     registers, the compiler would run this chain before the barrier and
   //     hold every partial sum until kl and kh are known.
 #pragma unroll
-  for (int u = 0; u < kItemsPerThread; ++u) x[u] = S.val[spos(tid * kItemsPerThread + u)];
+  for (int u = 0; u < kPartItems; ++u) x[u] = S.val[spos(tid * kPartItems + u)];
   int ul = -1, uh = -1;  // positions of those entries among the thread's items
   {
     uint32_t cl = 0, ch = 0;
 #pragma unroll
-    for (int u = 0; u < kItemsPerThread; ++u) {
+    for (int u = 0; u < kPartItems; ++u) {
       const uint32_t light = (lmask >> u) & 1u, heavy = (hmask >> u) & 1u;
       ul = (light && cl == kl) ? u : ul;
       uh = (heavy && ch == kh) ? u : uh;
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
   dd acc_l = dd_make(0.0, 0.0), acc_h = dd_make(0.0, 0.0);
   dd snap_l = dd_make(0.0, 0.0), snap_h = dd_make(0.0, 0.0);
 #pragma unroll
-  for (int u = 0; u < kItemsPerThread; ++u) {
+  for (int u = 0; u < kPartItems; ++u) {
     const bool light = (lmask >> u) & 1u;
     if (u == ul) snap_l = acc_l;
     if (u == uh) snap_h = acc_h;
@@ -724,7 +730,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
   __syncthreads();
   dd sl_off = dd_make(0.0, 0.0), sh_off = dd_make(0.0, 0.0);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kPartWaves; ++k) {
     if (k < wave) {
       sl_off = add_fast(sl_off, S.wl[k]);
       sh_off = add_fast(sh_off, S.wh[k]);
@@ -747,9 +753,9 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
 
   // 4. stage entries at their tile-local ranks (lights first, then heavies)
   uint32_t rl = rl0, rh = Lt + rh0;
-  const uint32_t li0 = (uint32_t)(lbase + (uint64_t)tid * kItemsPerThread);
+  const uint32_t li0 = (uint32_t)(lbase + (uint64_t)tid * kPartItems);
 #pragma unroll
-  for (int u = 0; u < kItemsPerThread; ++u) {
+  for (int u = 0; u < kPartItems; ++u) {
     const uint32_t light = (lmask >> u) & 1u, valid = (vmask >> u) & 1u;
     const uint32_t dst = light ? rl : rh;
     if (valid) {
@@ -763,7 +769,7 @@ __global__ __launch_bounds__(kTileThreads) void k_partition(Batch B) {
 
   // 5. coalesced write-out of both lists
   const uint32_t cnt = (uint32_t)((n - lbase < (uint64_t)kTileItems) ? n - lbase : kTileItems);
-  for (uint32_t e = tid; e < cnt; e += kTileThreads) {
+  for (uint32_t e = tid; e < cnt; e += kPartThreads) {
     if (e < Lt) {
       B.l_idx[off + l_before + e] = S.idx[e];
       B.l_w[off + l_before + e] = S.val[e];
@@ -1311,7 +1317,7 @@ int launch_build_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n1
   hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, B);
   hipLaunchKernelGGL(k_scan_group, dim3(groups), dim3(kScanThreads), 0, st, B);
   hipLaunchKernelGGL(k_scan_table, dim3(B.T), dim3(kScanThreads), 0, st, B);
-  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kTileThreads), 0, st, B);
+  hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kPartThreads), 0, st, B);
   launch_split(B, st);
   // one block per section: P = 64 * waves threads, G = C / P rows per thread
   const uint32_t waves = pack_waves_for(Lo.chunk, Lo.pack_waves);
