@@ -637,15 +637,7 @@ __global__ __launch_bounds__(kPartThreads) __attribute__((amdgpu_waves_per_eu(6)
   // 3a. block exclusive scans of the counts: this thread's first light and
   //     heavy ranks, hence which of its entries (if any) falls on a prefix
   //     point (every 64 entries of a list; at most one per list, G < 64)
-  uint32_t cl_inc = nl, ch_inc = nh;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t a = __shfl_up(cl_inc, d, 64), b = __shfl_up(ch_inc, d, 64);
-    if (lane >= d) {
-      cl_inc += a;
-      ch_inc += b;
-    }
-  }
+  const uint32_t cl_inc = wave_scan_u32(nl), ch_inc = wave_scan_u32(nh);
   if (lane == 63) {
     S.cl[wave] = cl_inc;
     S.ch[wave] = ch_inc;
@@ -714,15 +706,7 @@ __global__ __launch_bounds__(kPartThreads) __attribute__((amdgpu_waves_per_eu(6)
 
   // 3c. block exclusive scans of the sums (sums of nonnegative terms, so the
   //     same-sign addition add_fast is accurate)
-  dd sl_inc = acc_l, sh_inc = acc_h;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const dd ol = shfl_up(sl_inc, d), oh = shfl_up(sh_inc, d);
-    if (lane >= d) {
-      sl_inc = add_fast(ol, sl_inc);
-      sh_inc = add_fast(oh, sh_inc);
-    }
-  }
+  const dd sl_inc = wave_scan_dd(acc_l), sh_inc = wave_scan_dd(acc_h);
   if (lane == 63) {
     S.wl[wave] = sl_inc;
     S.wh[wave] = sh_inc;
@@ -736,11 +720,7 @@ __global__ __launch_bounds__(kPartThreads) __attribute__((amdgpu_waves_per_eu(6)
       sh_off = add_fast(sh_off, S.wh[k]);
     }
   }
-  dd sl_lane = shfl_up(sl_inc, 1), sh_lane = shfl_up(sh_inc, 1);
-  if (lane == 0) {
-    sl_lane = dd_make(0.0, 0.0);
-    sh_lane = dd_make(0.0, 0.0);
-  }
+  const dd sl_lane = wave_prev_dd(sl_inc), sh_lane = wave_prev_dd(sh_inc);
   const uint64_t ab = agg_base(off, t);
   if (kl < nl) {
     const uint64_t g = l_before + rl0 + kl;
@@ -1097,25 +1077,17 @@ __global__ __launch_bounds__(256) void k_pack(Batch B, TableOut out) {
       v = add_d(v, w[u]);
     }
   }
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const dd ov = shfl_up(v, d);
-    const int of = __shfl_up(f, d, 64);
-    if (lane >= d) {
-      if (!f) v = add_fast(ov, v);
-      f |= of;
-    }
+  {
+    uint32_t fu = (uint32_t)f;
+    wave_seg_scan_dd(v, fu);
+    f = (int)fu;
   }
   if (lane == 63) {
     s_wv[wave] = v;
     s_wf[wave] = f;
   }
-  dd cv = shfl_up(v, 1);
-  int cf = __shfl_up(f, 1, 64);
-  if (lane == 0) {
-    cv = dd_make(0.0, 0.0);
-    cf = 0;
-  }
+  dd cv = wave_prev_dd(v);                     // the previous lane's inclusive value
+  int cf = (int)wave_prev_u32((uint32_t)f);
   __syncthreads();
   {
     dd wv = dd_make(0.0, 0.0);  // combined totals of the earlier waves

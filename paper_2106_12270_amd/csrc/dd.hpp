@@ -188,4 +188,87 @@ __device__ __forceinline__ dd wave_sum_fast(dd v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Wave64 inclusive scans with DPP lane moves (VALU modifiers, no LDS
+// round trip): shifts of 1, 2, 4, 8 lanes inside each 16-lane row, then the
+// last lane of row 0 / row 2 into rows 1 / 3 (row_bcast:15) and the last lane
+// of row 1 into rows 2 and 3 (row_bcast:31).  Lanes without a source read 0,
+// the identity of every sum here.  The combination order is fixed, so the
+// result depends only on the inputs.
+// ---------------------------------------------------------------------------
+enum : int {
+  kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118,
+  kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138
+};
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xF, true);
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = dpp_u32<kCtrl, kRowMask>((uint32_t)v);
+  const uint32_t hi = dpp_u32<kCtrl, kRowMask>((uint32_t)(v >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __longlong_as_double((long long)dpp_u64<kCtrl, kRowMask>((uint64_t)__double_as_longlong(v)));
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ dd dpp_dd(dd v) {
+  return dd_make(dpp_f64<kCtrl, kRowMask>(v.hi), dpp_f64<kCtrl, kRowMask>(v.lo));
+}
+
+// one step of a (segmented) scan: this lane's (v, f) combined with the
+// DPP-moved value of an earlier lane: v stays if a segment starts here
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void dpp_seg_step(dd &v, uint32_t &f) {
+  const dd o = dpp_dd<kCtrl, kRowMask>(v);
+  const uint32_t of = dpp_u32<kCtrl, kRowMask>(f);
+  if (!f) v = add_fast(o, v);
+  f |= of;
+}
+
+// inclusive scan of same-sign dd values; f != 0 marks a lane whose value
+// starts a new segment (earlier lanes are not added to it or to later lanes)
+__device__ __forceinline__ void wave_seg_scan_dd(dd &v, uint32_t &f) {
+  dpp_seg_step<kDppRowShr1, 0xF>(v, f);
+  dpp_seg_step<kDppRowShr2, 0xF>(v, f);
+  dpp_seg_step<kDppRowShr4, 0xF>(v, f);
+  dpp_seg_step<kDppRowShr8, 0xF>(v, f);
+  dpp_seg_step<kDppRowBcast15, 0xA>(v, f);
+  dpp_seg_step<kDppRowBcast31, 0xC>(v, f);
+}
+
+// inclusive scan of same-sign dd values (no segments)
+__device__ __forceinline__ dd wave_scan_dd(dd v) {
+  v = add_fast(dpp_dd<kDppRowShr1, 0xF>(v), v);
+  v = add_fast(dpp_dd<kDppRowShr2, 0xF>(v), v);
+  v = add_fast(dpp_dd<kDppRowShr4, 0xF>(v), v);
+  v = add_fast(dpp_dd<kDppRowShr8, 0xF>(v), v);
+  v = add_fast(dpp_dd<kDppRowBcast15, 0xA>(v), v);
+  v = add_fast(dpp_dd<kDppRowBcast31, 0xC>(v), v);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t v) {
+  v += dpp_u32<kDppRowShr1, 0xF>(v);
+  v += dpp_u32<kDppRowShr2, 0xF>(v);
+  v += dpp_u32<kDppRowShr4, 0xF>(v);
+  v += dpp_u32<kDppRowShr8, 0xF>(v);
+  v += dpp_u32<kDppRowBcast15, 0xA>(v);
+  v += dpp_u32<kDppRowBcast31, 0xC>(v);
+  return v;
+}
+
+// the value of the previous lane (0 in lane 0)
+__device__ __forceinline__ dd wave_prev_dd(dd v) { return dpp_dd<kDppWaveShr1, 0xF>(v); }
+__device__ __forceinline__ uint32_t wave_prev_u32(uint32_t v) {
+  return dpp_u32<kDppWaveShr1, 0xF>(v);
+}
+
 }  // namespace amdalias
