@@ -42,6 +42,10 @@ def parse():
                     help="skip the learned-vs-binary split comparison")
     ap.add_argument("--no-sectioned", action="store_true",
                     help="skip the sectioned-sampling measurement")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched-table workloads (profiling)")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="skip the per-table loop comparison of the batched workloads")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-table workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +323,12 @@ def main():
         print(json.dumps({"copy_calibration_bytes": src.numel() * 8}))
         return
 
+    if args.batched_only:
+        res = [batched(pkg, inputs, b, per_table_loop=not args.no_loop, learned=lrn)
+               for b, lrn in (("batch_100k_16_65536", False), ("batch_1024_2p14_2p22", True))]
+        print(json.dumps({"batched": res}), flush=True)
+        return
+
     cfg = inputs.WORKLOADS[args.workload]
     n = cfg["n"]
     draws = cfg["draws"] if args.draws is None else args.draws
@@ -462,11 +472,10 @@ def main():
         print("[bench] learned vs binary split", file=sys.stderr, flush=True)
         result["learned_vs_binary"] = learned_vs_binary(pkg, inputs)
     if not args.no_batched:
-        for bname, loop, lrn in (("batch_100k_16_65536", True, False),
-                                 ("batch_1024_2p14_2p22", True, True)):
+        for bname, lrn in (("batch_100k_16_65536", False), ("batch_1024_2p14_2p22", True)):
             print(f"[bench] batched {bname}", file=sys.stderr, flush=True)
             result.setdefault("batched", []).append(
-                batched(pkg, inputs, bname, per_table_loop=loop, learned=lrn))
+                batched(pkg, inputs, bname, per_table_loop=not args.no_loop, learned=lrn))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_n, args.cpu_draws)
