@@ -599,13 +599,25 @@ def sample_batched_rows(rows, offsets, draw_offsets, seed, out, status=None, str
 # ---------------------------------------------------------------------------
 # Sectioned sampling
 # ---------------------------------------------------------------------------
+def default_section_log2(n, max_sections=8192):
+    """Smallest section size 2^r (r >= 6) that leaves at most `max_sections`
+    sections (the counts then fit the counting kernel's LDS histogram)."""
+    r = 6
+    while (int(n) + (1 << r) - 1) >> r > max_sections:
+        r += 1
+    return r
+
+
 class SectionedSampler:
     """Owns the workspace of sectioned sampling for (n, count, log2r): the
-    draws grouped by table section of 2^log2r rows (see the C header)."""
+    draws grouped by table section of 2^log2r rows (see the C header).
+    log2r=None picks default_section_log2(n)."""
 
-    def __init__(self, n, count, log2r, device="cuda"):
+    def __init__(self, n, count, log2r=None, device="cuda"):
         import torch
 
+        if log2r is None:
+            log2r = default_section_log2(n)
         self.n, self.count, self.log2r = int(n), int(count), int(log2r)
         b = lib().alias_sample_sectioned_workspace_bytes(self.n, self.count, self.log2r)
         if b == 0:

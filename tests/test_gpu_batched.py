@@ -410,3 +410,30 @@ def test_every_pack_shape_builds_the_oracle_table(chunk, waves):
         s, e = int(off[t]), int(off[t + 1])
         op, oa = oracle.psa_build(wt, chunk=chunk)
         assert np.array_equal(a[s:e], oa) and np.array_equal(p[s:e], op), t
+
+
+def test_full_size_batch_exact_integers_bitwise():
+    """The 100k-table batch shape with exact-arithmetic weights: sampled tables
+    equal the oracle's bit for bit."""
+    sizes = inputs.log_uniform_sizes(100_000, 16, 65536, seed=inputs.weight_seed(4))
+    say("full batch exact", len(sizes), int(sizes.sum()))
+    rng = np.random.default_rng(77)
+    # per table: integer weights whose total is a multiple of the table size
+    w = rng.integers(0, 1 << 20, size=int(sizes.sum())).astype(np.float64)
+    off = inputs.offsets_from_sizes(sizes)
+    ends = off[1:].astype(np.int64) - 1
+    starts = off[:-1].astype(np.int64)
+    tot = np.add.reduceat(w, starts)
+    w[ends] += (sizes - (tot.astype(np.int64) % sizes)) % sizes
+    T = len(sizes)
+    bb = pkg.BatchBuilder(T, len(w), 1024, device=DEV)
+    rows = bb.build_rows(torch.from_numpy(w).to(DEV), dev_u64(off))
+    torch.cuda.synchronize()
+    assert (bb.status == 0).all()
+    picks = sorted(set(rng.integers(0, T, 40).tolist()) | {0, T - 1})
+    for t in picks:
+        s, e = int(off[t]), int(off[t + 1])
+        pr, al = pkg.rows_split(rows[s:e])
+        op, oa = oracle.psa_build(w[s:e], chunk=1024)
+        assert np.array_equal(al.cpu().numpy().view(np.uint32), oa), t
+        assert np.array_equal(pr.cpu().numpy(), op), t

@@ -275,3 +275,24 @@ def test_fullsize_powerlaw_2p27_table_equals_oracle():
     op, oa = oracle.psa_build(w, chunk=cfg["chunk"])
     assert np.array_equal(a, oa)
     assert ulp_diff(p, op).max() <= 2
+
+
+def test_fullsize_exact_integers_bitwise():
+    """Exact-arithmetic weights at the full 2^27 size in the benchmark's
+    launch configuration (chunk 1024, rows): every sum is exact in dd, so the
+    table must equal the oracle's bit for bit, including the section splits."""
+    n = 1 << 27
+    say("fullsize exact 2^27")
+    w = inputs.exact_integers(n, seed=2027, max_w=1 << 20, zero_frac=0.01)
+    b = pkg.Builder(n, 1024, device=DEV)
+    rows = b.build_rows(torch.from_numpy(w).to(DEV))
+    torch.cuda.synchronize()
+    assert int(b.status.item()) == 0
+    pr, al = pkg.rows_split(rows)
+    p = pr.cpu().numpy()
+    a = al.cpu().numpy().view(np.uint32)
+    op, oa, info = oracle.psa_build(w, chunk=1024, with_splits=True)
+    assert np.array_equal(a, oa)
+    assert np.array_equal(p, op)
+    it = b.intermediates()
+    assert np.array_equal(it["split_j"], info["split_j"].astype(np.uint32))
