@@ -444,7 +444,7 @@ def main():
     # same table: the 10^9 draws again, timed on the same stream
     if rows_layout and not args.no_sectioned:
         sec = {}
-        for log2r in (14, 16, 18):
+        for log2r in (13, 14, 16):
             ss = pkg.SectionedSampler(n, draws, log2r, device=dev)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, out=out, stream=stream)

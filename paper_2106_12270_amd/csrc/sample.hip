@@ -63,6 +63,18 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(const double *__restr
   }
 }
 
+// A row read that is not expected to be reused (a random gather from a
+// table much larger than the caches): a non-temporal 128-bit load.
+__device__ __forceinline__ TableRow load_row_stream(const TableRow *p) {
+  typedef unsigned int u32v4 __attribute__((ext_vector_type(4)));
+  const u32v4 v = __builtin_nontemporal_load((const u32v4 *)p);
+  TableRow r;
+  r.prob = __hiloint2double((int)v.y, (int)v.x);
+  r.alias = v.z;
+  r.pad = v.w;
+  return r;
+}
+
 // The same draws from a table of 16-byte rows: one 128-bit gather per draw
 // instead of one for prob and another for alias.
 __global__ __launch_bounds__(kSampleThreads) void k_sample_rows(const TableRow *__restrict__ rows,
@@ -79,10 +91,11 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_rows(const TableRow *
 #pragma unroll
     for (int u = 0; u < kSampleUnroll; ++u) draw_setup(first + q + u * G, table, k0, k1, n, row[u], coin[u]);
 #pragma unroll
-    for (int u = 0; u < kSampleUnroll; ++u) t[u] = rows[row[u]];
+    for (int u = 0; u < kSampleUnroll; ++u) t[u] = load_row_stream(&rows[row[u]]);
 #pragma unroll
     for (int u = 0; u < kSampleUnroll; ++u)
-      out[q + u * G] = (coin[u] < t[u].prob) ? (uint32_t)row[u] : t[u].alias;
+      __builtin_nontemporal_store((coin[u] < t[u].prob) ? (uint32_t)row[u] : t[u].alias,
+                                  &out[q + u * G]);
   }
   for (; q < count; q += G) {
     uint64_t row;
@@ -237,8 +250,8 @@ int launch_sample_batched(const double *prob, const uint32_t *alias, const Table
 //                of a section read rows of one R-row range, which stays in L2.
 // ---------------------------------------------------------------------------
 constexpr int kSecThreads = 256;
-constexpr uint32_t kSecItem = 4096;       // draws per work item
-constexpr uint32_t kSecLdsHist = 8192;    // sections counted in LDS (else in global memory)
+constexpr uint32_t kSecItem = 8192;       // draws per work item
+constexpr uint32_t kSecLdsHist = 16384;   // sections counted in LDS (else in global memory)
 
 struct SecLayout {
   uint64_t counts, offsets, work, total;  // byte offsets in the workspace
@@ -463,8 +476,12 @@ int launch_sample_sectioned(const double *prob, const uint32_t *alias, const Tab
   hipLaunchKernelGGL(k_sec_count, dim3((uint32_t)cb), dim3(kSecThreads), 0, st, n, count, log2r,
                      L.S, k0, k1, table, (unsigned long long *)counts);
   hipLaunchKernelGGL(k_sec_scan, dim3(1), dim3(1024), 0, st, counts, L.S, offsets, work);
+  // Few blocks (one per CU), each drawing kSecItem samples per work item:
+  // the fewer work items in flight, the fewer sections whose rows compete
+  // for an XCD's L2 (measured best on the 2^27-row table against 4x-16x
+  // more blocks or larger blocks).
   uint64_t db = count / kSecItem + L.S;
-  if (db > 4096) db = 4096;
+  if (db > 256) db = 256;
   db = (db + 7) / 8 * 8;  // eight XCD classes of blocks
   if (db == 0) db = 8;
   if (rows)
