@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SECTION_LOG2R_BATCH = 13  # rows per section of batched sectioned sampling: 2^13
 # algorithmic bytes of the build per item: read w twice (16: total weight,
 # then partition), write the light/heavy lists with weights (12), read them in
 # the pack (12), write the table row (8 + 4)
@@ -260,6 +261,35 @@ def batched(pkg, inputs, name, per_table_loop=False, learned=False, reps=5, epoc
     with torch.cuda.graph(g):
         step()
     out["graph_ms"] = round(timed(g.replay, reps), 4)
+    del g
+    # batched sectioned sampling (Sec. 5 sectioned methods over the batch):
+    # the same draw counts, grouped by table section of 2^13 rows
+    bs = pkg.BatchedSectionedSampler(T, total, nd, SECTION_LOG2R_BATCH, device=dev)
+
+    def sec():
+        bs.sample_rows(rows, od, dd_, inputs.SAMPLE_SEED, res)
+
+    sec()
+    torch.cuda.synchronize()
+    if int(bs.status.item()):
+        raise SystemExit(f"{name}: batched sectioned sample failed")
+    out["sectioned_log2r"] = SECTION_LOG2R_BATCH
+    out["sectioned_sample_ms"] = round(timed(sec, reps), 4)
+    out["sectioned_samples_per_s"] = nd / (out["sectioned_sample_ms"] * 1e-3)
+
+    def step_sec():
+        bb.build_rows(w, od, rows=rows)
+        sec()
+
+    with torch.cuda.stream(s2):
+        step_sec()
+    stream.wait_stream(s2)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step_sec()
+    out["graph_sectioned_ms"] = round(timed(g.replay, reps), 4)
+    del g, bs
     out["build_items_per_s"] = total / (out["build_ms"] * 1e-3)
     out["build_hbm_frac"] = round(total * BUILD_BYTES_PER_ITEM / (out["build_ms"] * 1e-3)
                                   / (HBM_PEAK_GBS * 1e9), 4)

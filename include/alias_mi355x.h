@@ -286,6 +286,44 @@ int alias_sample_batched_rows(const void *d_rows, const uint64_t *d_offsets, uin
                               uint64_t total_draws, uint64_t seed, uint32_t *d_out,
                               int32_t *d_status, void *stream);
 
+/* Batched sectioned sampling (Sec. 5, the sectioned methods, over a batch):
+ * every table of the batch sampled section by section in one fixed launch
+ * sequence (no host synchronisation; capturable into a HIP graph).  Table
+ * t's output range [draw_offsets[t], draw_offsets[t+1]) holds exactly what
+ * alias_sample_sectioned writes for that table alone with
+ * count = draw_offsets[t+1] - draw_offsets[t], the same seed and log2r, and
+ * table_id t: its draws grouped by section of 2^log2r rows, as table-local
+ * item ids.  The sections of all tables share one counting pass and one
+ * drawing pass, so many small tables cost no more launches than one.
+ *
+ * Workspace bytes (0 if invalid: T not in [1, 2^20], total_items not in
+ * [1, 2^40], total_draws > 2^40, log2r not in [6, 31], or more than
+ * 2^32 - 1 sections in all). */
+size_t alias_sample_batched_sectioned_workspace_bytes(uint32_t T, uint64_t total_items,
+                                                      uint64_t total_draws, uint32_t log2r);
+
+/* Batched sectioned sampling from two-array tables.
+ *   d_offsets, d_draw_offsets   as for alias_sample_batched
+ *   d_out       device, total_draws uint32 (may be NULL when total_draws = 0)
+ *   d_ws        device workspace of the size above, 256-byte aligned
+ *   d_status    device int32: ALIAS_OK, or ALIAS_EINVAL if the offsets are
+ *               inconsistent (then every output is 0xFFFFFFFF) or a table
+ *               with draws has no items or more than 2^32 - 1 (its draws are
+ *               0xFFFFFFFF; no row outside the batch is read).
+ * Returns ALIAS_OK, ALIAS_EINVAL, ALIAS_EWORKSPACE or ALIAS_EHIP. */
+int alias_sample_batched_sectioned(const double *d_prob, const uint32_t *d_alias,
+                                   const uint64_t *d_offsets, uint32_t T, uint64_t total_items,
+                                   const uint64_t *d_draw_offsets, uint64_t total_draws,
+                                   uint64_t seed, uint32_t log2r, uint32_t *d_out, void *d_ws,
+                                   size_t ws_bytes, int32_t *d_status, void *stream);
+
+/* The same draws from a batch of 16-byte rows (d_rows 16-byte aligned). */
+int alias_sample_batched_sectioned_rows(const void *d_rows, const uint64_t *d_offsets, uint32_t T,
+                                        uint64_t total_items, const uint64_t *d_draw_offsets,
+                                        uint64_t total_draws, uint64_t seed, uint32_t log2r,
+                                        uint32_t *d_out, void *d_ws, size_t ws_bytes,
+                                        int32_t *d_status, void *stream);
+
 /* ------------------------------------------------------------------------
  * Autotuning (an added system pattern): the rows per section (chunk_items)
  * and the waves that pack one section (pack_waves) are timed on the device

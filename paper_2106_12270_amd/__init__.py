@@ -127,6 +127,14 @@ def lib():
         L.alias_sample_sectioned_rows.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp,
                                                   C.c_size_t, vp]
         L.alias_sample_sectioned_rows.restype = C.c_int
+        L.alias_sample_batched_sectioned_workspace_bytes.argtypes = [u32, u64, u64, u32]
+        L.alias_sample_batched_sectioned_workspace_bytes.restype = C.c_size_t
+        L.alias_sample_batched_sectioned.argtypes = [vp, vp, vp, u32, u64, vp, u64, u64, u32, vp,
+                                                     vp, C.c_size_t, vp, vp]
+        L.alias_sample_batched_sectioned.restype = C.c_int
+        L.alias_sample_batched_sectioned_rows.argtypes = [vp, vp, u32, u64, vp, u64, u64, u32,
+                                                          vp, vp, C.c_size_t, vp, vp]
+        L.alias_sample_batched_sectioned_rows.restype = C.c_int
         L.alias_status_str.argtypes = [C.c_int]
         L.alias_status_str.restype = C.c_char_p
         L.alias_version.argtypes = []
@@ -656,3 +664,55 @@ class SectionedSampler:
         if st:
             raise AliasError(st, "alias_sample_sectioned")
         return out
+
+
+class BatchedSectionedSampler:
+    """Owns the workspace of batched sectioned sampling: T tables holding
+    total_items rows in all, total_draws draws in all, sections of 2^log2r
+    rows (see the C header).  Table t's output range holds exactly what
+    SectionedSampler gives for that table alone with table_id t."""
+
+    def __init__(self, T, total_items, total_draws, log2r=13, device="cuda"):
+        import torch
+
+        self.T, self.total_items = int(T), int(total_items)
+        self.total_draws, self.log2r = int(total_draws), int(log2r)
+        b = lib().alias_sample_batched_sectioned_workspace_bytes(
+            self.T, self.total_items, self.total_draws, self.log2r)
+        if b == 0:
+            raise AliasError(ALIAS_EINVAL, "alias_sample_batched_sectioned_workspace_bytes")
+        self.ws_bytes = b
+        self.ws = torch.empty(b, dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def _args(self, offsets, draw_offsets, total_items, out, device):
+        T, _ = _sample_batched_args(offsets, draw_offsets, total_items, out, self.status, device)
+        if T != self.T or total_items != self.total_items or out.numel() != self.total_draws:
+            raise ValueError("batch shape differs from the sampler's")
+        return T
+
+    def sample_rows(self, rows, offsets, draw_offsets, seed, out, stream=None):
+        """Returns (out, status); status is a 1-element int32 device tensor."""
+        _check_rows(rows, rows.shape[0])
+        T = self._args(offsets, draw_offsets, rows.shape[0], out, rows.device)
+        st = lib().alias_sample_batched_sectioned_rows(
+            _ptr(rows), _ptr(offsets), T, rows.shape[0], _ptr(draw_offsets), out.numel(),
+            int(seed) & (2**64 - 1), self.log2r, _ptr(out), _ptr(self.ws), self.ws_bytes,
+            _ptr(self.status), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_sample_batched_sectioned_rows")
+        return out, self.status
+
+    def sample(self, prob, alias, offsets, draw_offsets, seed, out, stream=None):
+        import torch
+
+        _check_dev(prob, torch.float64, "prob")
+        _check_dev(alias, torch.int32, "alias")
+        T = self._args(offsets, draw_offsets, prob.numel(), out, prob.device)
+        st = lib().alias_sample_batched_sectioned(
+            _ptr(prob), _ptr(alias), _ptr(offsets), T, prob.numel(), _ptr(draw_offsets),
+            out.numel(), int(seed) & (2**64 - 1), self.log2r, _ptr(out), _ptr(self.ws),
+            self.ws_bytes, _ptr(self.status), _stream(stream))
+        if st:
+            raise AliasError(st, "alias_sample_batched_sectioned")
+        return out, self.status

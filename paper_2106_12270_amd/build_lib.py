@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libalias_mi355x.so")
-SOURCES = ["build.hip", "sample.hip", "learn.hip", "abi.hip"]
+SOURCES = ["build.hip", "sample.hip", "sample_sections.hip", "learn.hip", "abi.hip"]
 ARCH = os.environ.get("ALIAS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -21,6 +21,14 @@ int launch_sample_batched(const double *prob, const uint32_t *alias, const Table
                           uint64_t total_items, uint64_t total_draws, uint64_t seed,
                           uint32_t *out, int32_t *status, hipStream_t st);
 size_t sec_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r);
+size_t bs_workspace_bytes(uint32_t T, uint64_t total_items, uint64_t total_draws,
+                          uint32_t log2r);
+int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
+                                    const TableRow *rows, const uint64_t *offsets,
+                                    const uint64_t *draw_off, uint32_t T, uint64_t total_items,
+                                    uint64_t total_draws, uint64_t seed, uint32_t log2r,
+                                    uint32_t *out, void *d_ws, size_t ws_bytes, int32_t *status,
+                                    uint32_t draw_blocks, hipStream_t st);
 int launch_sample_sectioned(const double *prob, const uint32_t *alias, const TableRow *rows,
                             uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
                             uint32_t log2r, uint32_t *out, uint64_t *d_counts, void *d_ws,
@@ -254,6 +262,55 @@ int alias_sample_sectioned_rows(const void *d_rows, uint64_t n, uint64_t count, 
   return launch_sample_sectioned(nullptr, nullptr, (const TableRow *)d_rows, n, count, seed,
                                  table_id, log2r, d_out, d_counts, d_ws, ws_bytes,
                                  (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sectioned sampling
+// ---------------------------------------------------------------------------
+size_t alias_sample_batched_sectioned_workspace_bytes(uint32_t T, uint64_t total_items,
+                                                      uint64_t total_draws, uint32_t log2r) {
+  return bs_workspace_bytes(T, total_items, total_draws, log2r);
+}
+
+static int batched_sectioned_common(const uint64_t *d_offsets, uint32_t T, uint64_t total_items,
+                                    const uint64_t *d_draw_offsets, uint64_t total_draws,
+                                    uint32_t log2r, const uint32_t *d_out, const void *d_ws,
+                                    const int32_t *d_status) {
+  if (bs_workspace_bytes(T, total_items, total_draws, log2r) == 0) return ALIAS_EINVAL;
+  if (!d_offsets || !d_draw_offsets || !d_ws || !d_status || (total_draws && !d_out))
+    return ALIAS_EINVAL;
+  if (!aligned(d_offsets, 8) || !aligned(d_draw_offsets, 8) || !aligned(d_out, 4) ||
+      !aligned(d_ws, 256) || !aligned(d_status, 4))
+    return ALIAS_EINVAL;
+  return ALIAS_OK;
+}
+
+int alias_sample_batched_sectioned(const double *d_prob, const uint32_t *d_alias,
+                                   const uint64_t *d_offsets, uint32_t T, uint64_t total_items,
+                                   const uint64_t *d_draw_offsets, uint64_t total_draws,
+                                   uint64_t seed, uint32_t log2r, uint32_t *d_out, void *d_ws,
+                                   size_t ws_bytes, int32_t *d_status, void *stream) {
+  if (!d_prob || !d_alias || !aligned(d_prob, 8) || !aligned(d_alias, 4)) return ALIAS_EINVAL;
+  const int st = batched_sectioned_common(d_offsets, T, total_items, d_draw_offsets, total_draws,
+                                          log2r, d_out, d_ws, d_status);
+  if (st) return st;
+  return launch_sample_batched_sectioned(d_prob, d_alias, nullptr, d_offsets, d_draw_offsets, T,
+                                         total_items, total_draws, seed, log2r, d_out, d_ws,
+                                         ws_bytes, d_status, 0, (hipStream_t)stream);
+}
+
+int alias_sample_batched_sectioned_rows(const void *d_rows, const uint64_t *d_offsets, uint32_t T,
+                                        uint64_t total_items, const uint64_t *d_draw_offsets,
+                                        uint64_t total_draws, uint64_t seed, uint32_t log2r,
+                                        uint32_t *d_out, void *d_ws, size_t ws_bytes,
+                                        int32_t *d_status, void *stream) {
+  if (!d_rows || !aligned(d_rows, 16)) return ALIAS_EINVAL;
+  const int st = batched_sectioned_common(d_offsets, T, total_items, d_draw_offsets, total_draws,
+                                          log2r, d_out, d_ws, d_status);
+  if (st) return st;
+  return launch_sample_batched_sectioned(nullptr, nullptr, (const TableRow *)d_rows, d_offsets,
+                                         d_draw_offsets, T, total_items, total_draws, seed, log2r,
+                                         d_out, d_ws, ws_bytes, d_status, 0, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,11 +6,13 @@
 //   k_setup_*        per table: number of 4096-item tiles, of C-row sections
 //                    and of 1024-tile groups, their prefix sums; headers reset.
 //   k_reduce_tile    per tile: double-double sum of the weights + validation.
-//   k_reduce_group   per tile group: sum of its tiles' sums.
-//   k_finalize       per table: W, W/N, status (fixed combination order).
+//   k_reduce_group   per tile group (one wave): sum of its tiles' sums.
+//   k_finalize       per table (one wave): W, W/N, status.
 //   k_tilesum        per tile: light count, light and heavy weight sums.
-//   k_scan_group     per tile group: exclusive prefix of its tiles' sums.
-//   k_scan_table     per table: exclusive prefix of its groups' sums; L, H.
+//   k_scan_group     per tile group (one wave): exclusive prefix of its
+//                    tiles' sums.
+//   k_scan_table     per table (one wave): exclusive prefix of its groups'
+//                    sums; L, H.
 //   k_partition      per tile: stable light/heavy partition in item order;
 //                    entries carry their weight (Sec. 4.2 "Weight in l and h
 //                    Arrays"); prefix sums emitted every 64 entries.
@@ -284,32 +286,32 @@ __global__ __launch_bounds__(kTileThreads) void k_reduce_tile(Batch B) {
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce_group: dd sum of a tile group's tile sums (fixed order)
+// k_reduce_group: dd sum of a tile group's tile sums, one wave per group
+// (lane l adds tiles l, l + 64, ...; then a fixed butterfly)
 // ---------------------------------------------------------------------------
+constexpr int kWaveItemsPerBlock = 4;  // groups or tables per 256-thread block
+
 __global__ __launch_bounds__(256) void k_reduce_group(Batch B) {
-  __shared__ dd s_wave[4];
-  __shared__ uint32_t s_bad;
   if (B.flags[0]) return;
-  const uint64_t g = blockIdx.x;
-  if (g >= B.grp_start[B.T]) return;
-  if (threadIdx.x == 0) s_bad = 0;
+  const int lane = threadIdx.x & 63;
+  const uint64_t g = (uint64_t)blockIdx.x * kWaveItemsPerBlock + (threadIdx.x >> 6);
+  if (g >= B.grp_start[B.T]) return;  // uniform over the wave
   uint64_t k0, k1;
   group_tiles(B, g, &k0, &k1);
-  __syncthreads();
   dd s = dd_make(0.0, 0.0);
   uint32_t bad = 0;
-  for (uint64_t k = k0 + threadIdx.x * 4; k < k0 + threadIdx.x * 4 + 4 && k < k1; ++k) {
+  for (uint64_t k = k0 + lane; k < k1; k += 64) {
     const ReducePart p = B.tilew[k];
     s = add_fast(s, dd_make(p.hi, p.lo));
     bad |= p.bad;
   }
-  if (bad) atomicOr(&s_bad, 1u);
-  const dd tot = block_sum_dd(s, s_wave);
-  if (threadIdx.x == 0) {
+  const dd tot = wave_sum_fast(s);
+  const bool any_bad = __ballot(bad != 0) != 0;
+  if (lane == 0) {
     ReducePart p;
     p.hi = tot.hi;
     p.lo = tot.lo;
-    p.bad = s_bad;
+    p.bad = any_bad ? 1u : 0u;
     p.pad = 0;
     p.pad2 = 0.0;
     B.grpw[g] = p;
@@ -317,36 +319,34 @@ __global__ __launch_bounds__(256) void k_reduce_group(Batch B) {
 }
 
 // ---------------------------------------------------------------------------
-// k_finalize: per table W, W/N, status (one block per table, over its groups)
+// k_finalize: per table W, W/N, status (one wave per table, over its groups)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(Batch B) {
-  __shared__ dd s_wave[4];
-  __shared__ uint32_t s_bad;
-  const uint32_t t = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint64_t t = (uint64_t)blockIdx.x * kWaveItemsPerBlock + (threadIdx.x >> 6);
+  if (t >= B.T) return;  // uniform over the wave
   if (B.flags[0]) {  // inconsistent batch description: every table fails, nothing is built
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       B.hdr[t].status = ALIAS_EINVAL;
       B.status[t] = ALIAS_EINVAL;
     }
     return;
   }
   if (B.hdr[t].status != ALIAS_OK) return;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
   const uint64_t g0 = B.grp_start[t], g1 = B.grp_start[t + 1];
   dd s = dd_make(0.0, 0.0);
   uint32_t bad = 0;
-  for (uint64_t k = g0 + threadIdx.x; k < g1; k += blockDim.x) {
+  for (uint64_t k = g0 + lane; k < g1; k += 64) {
     const ReducePart p = B.grpw[k];
     s = add_fast(s, dd_make(p.hi, p.lo));
     bad |= p.bad;
   }
-  if (bad) atomicOr(&s_bad, 1u);
-  const dd W = block_sum_dd(s, s_wave);
-  if (threadIdx.x == 0) {
+  const dd W = wave_sum_fast(s);
+  const bool any_bad = __ballot(bad != 0) != 0;
+  if (lane == 0) {
     uint64_t off, n;
-    table_range(B, t, off, n);
-    const bool ok = !s_bad && (W.hi > 0.0) && (W.hi < INFINITY);
+    table_range(B, (uint32_t)t, off, n);
+    const bool ok = !any_bad && (W.hi > 0.0) && (W.hi < INFINITY);
     const dd avg = ok ? div_d(W, (double)n) : dd_make(0.0, 0.0);
     alias_ws_header *h = &B.hdr[t];
     h->W_hi = W.hi;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B) {
     h->avg_lo = avg.lo;
     h->status = ok ? ALIAS_OK : ALIAS_EWEIGHTS;
     B.status[t] = h->status;
-    const uint64_t ab = agg_base(off, t);
+    const uint64_t ab = agg_base(off, (uint32_t)t);
     B.agg_l[ab] = dd_make(0.0, 0.0);
     B.agg_h[ab] = dd_make(0.0, 0.0);
   }
@@ -428,13 +428,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tilesum(Batch B) {
 }
 
 // ---------------------------------------------------------------------------
-// k_tilescan: per table (one block), exclusive prefix of its tiles' sums in
-// chunks of 4 tiles per thread; table totals; the final prefix-sum points
-// when a list length is a multiple of the stride.
+// Scans of tile sums (light count, light and heavy dd sums)
 // ---------------------------------------------------------------------------
-constexpr int kScanThreads = 256;
-constexpr int kScanPer = kScanTiles / kScanThreads;  // 4 tiles per thread
-
 struct ScanVal {
   uint64_t c;
   dd l, h;
@@ -482,86 +477,70 @@ __device__ __forceinline__ TilePrefix tp_of(const ScanVal &v) {
   return p;
 }
 
-// exclusive scan over a kScanThreads block; *total gets the block total
-__device__ __forceinline__ ScanVal block_exscan(ScanVal v, ScanVal *s_w, ScanVal *total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  ScanVal inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const dd ol = shfl_up(inc.l, d), oh = shfl_up(inc.h, d);
-    const uint64_t oc = __shfl_up(inc.c, d, 64);
-    if (lane >= d) {
-      inc.l = add_fast(ol, inc.l);
-      inc.h = add_fast(oh, inc.h);
-      inc.c += oc;
-    }
+// One wave scans a run of ScanVals in chunks of 64 (one per lane): DPP
+// inclusive scans of the chunk, the previous lane's value as the exclusive
+// prefix, lane 63's as the chunk total, and a carry across chunks (a fixed
+// combination order).  Every lane of the wave takes part.
+struct WaveScan {
+  ScanVal carry;
+  __device__ __forceinline__ ScanVal step(const ScanVal &v) {
+    const uint32_t c = wave_scan_u32((uint32_t)v.c);
+    const dd l = wave_scan_dd(v.l), h = wave_scan_dd(v.h);
+    ScanVal ex;
+    ex.c = wave_prev_u32(c);
+    ex.l = wave_prev_dd(l);
+    ex.h = wave_prev_dd(h);
+    const ScanVal out = sv_add(carry, ex);
+    ScanVal tot;
+    tot.c = (uint32_t)__shfl((int)c, 63, 64);
+    tot.l = shfl(l, 63);
+    tot.h = shfl(h, 63);
+    carry = sv_add(carry, tot);
+    return out;
   }
-  if (lane == 63) s_w[wave] = inc;
-  ScanVal ex;
-  ex.l = shfl_up(inc.l, 1);
-  ex.h = shfl_up(inc.h, 1);
-  ex.c = __shfl_up(inc.c, 1, 64);
-  if (lane == 0) ex = sv_zero();
-  __syncthreads();
-  ScanVal off = sv_zero(), tot = sv_zero();
-  for (int k = 0; k < kScanThreads / 64; ++k) {
-    if (k < wave) off = sv_add(off, s_w[k]);
-    tot = sv_add(tot, s_w[k]);
-  }
-  __syncthreads();
-  *total = tot;
-  return sv_add(off, ex);
-}
+};
 
-// k_scan_group: per tile group, the exclusive prefix of its tiles' sums
-// (group-local) and the group's totals.
-__global__ __launch_bounds__(kScanThreads) void k_scan_group(Batch B) {
-  __shared__ ScanVal s_w[kScanThreads / 64];
+// k_scan_group: per tile group (one wave each), the exclusive prefix of its
+// tiles' sums (group-local) and the group's totals.
+__global__ __launch_bounds__(256) void k_scan_group(Batch B) {
   if (B.flags[0]) return;
-  const uint64_t g = blockIdx.x;
-  if (g >= B.grp_start[B.T]) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t g = (uint64_t)blockIdx.x * kWaveItemsPerBlock + (threadIdx.x >> 6);
+  if (g >= B.grp_start[B.T]) return;  // uniform over the wave
   uint64_t k0, k1;
   const uint32_t t = group_tiles(B, g, &k0, &k1);
   if (B.hdr[t].status != ALIAS_OK) return;
-  const uint64_t b = k0 + (uint64_t)threadIdx.x * kScanPer;
-  ScanVal v[kScanPer];
-  ScanVal mine = sv_zero();
-#pragma unroll
-  for (int u = 0; u < kScanPer; ++u) {
-    v[u] = (b + u < k1) ? sv_of(B.tsum[b + u]) : sv_zero();
-    mine = sv_add(mine, v[u]);
+  WaveScan ws;
+  ws.carry = sv_zero();
+  for (uint64_t c0 = k0; c0 < k1; c0 += 64) {
+    const uint64_t k = c0 + lane;
+    const ScanVal ex = ws.step(k < k1 ? sv_of(B.tsum[k]) : sv_zero());
+    if (k < k1) B.tpre[k] = tp_of(ex);
   }
-  ScanVal tot;
-  ScanVal run = block_exscan(mine, s_w, &tot);
-#pragma unroll
-  for (int u = 0; u < kScanPer; ++u) {
-    if (b + u < k1) B.tpre[b + u] = tp_of(run);
-    run = sv_add(run, v[u]);
-  }
-  if (threadIdx.x == 0) B.gsum[g] = tp_of(tot);
+  if (lane == 0) B.gsum[g] = tp_of(ws.carry);
 }
 
-// k_scan_table: per table, the exclusive prefix of its groups' totals, the
-// table's light count and sums, and the final prefix-sum points when a list
-// length is a multiple of the stride.
-__global__ __launch_bounds__(kScanThreads) void k_scan_table(Batch B) {
-  __shared__ ScanVal s_w[kScanThreads / 64];
+// k_scan_table: per table (one wave each), the exclusive prefix of its
+// groups' totals, the table's light count and sums, and the final
+// prefix-sum points when a list length is a multiple of the stride.
+__global__ __launch_bounds__(256) void k_scan_table(Batch B) {
   if (B.flags[0]) return;
-  const uint32_t t = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint64_t t = (uint64_t)blockIdx.x * kWaveItemsPerBlock + (threadIdx.x >> 6);
+  if (t >= B.T) return;  // uniform over the wave
   if (B.hdr[t].status != ALIAS_OK) return;
   const uint64_t g0 = B.grp_start[t], g1 = B.grp_start[t + 1];
-  ScanVal carry = sv_zero();
-  for (uint64_t c0 = g0; c0 < g1; c0 += kScanThreads) {
-    const uint64_t g = c0 + threadIdx.x;
-    const ScanVal mine = (g < g1) ? sv_of(B.gsum[g]) : sv_zero();
-    ScanVal tot;
-    const ScanVal ex = sv_add(carry, block_exscan(mine, s_w, &tot));
+  WaveScan ws;
+  ws.carry = sv_zero();
+  for (uint64_t c0 = g0; c0 < g1; c0 += 64) {
+    const uint64_t g = c0 + lane;
+    const ScanVal ex = ws.step(g < g1 ? sv_of(B.gsum[g]) : sv_zero());
     if (g < g1) B.gpre[g] = tp_of(ex);
-    carry = sv_add(carry, tot);
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
+    const ScanVal carry = ws.carry;
     uint64_t off, n;
-    table_range(B, t, off, n);
+    table_range(B, (uint32_t)t, off, n);
     const uint64_t L = carry.c, H = n - carry.c;
     alias_ws_header *h = &B.hdr[t];
     h->L = L;
@@ -570,7 +549,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_table(Batch B) {
     h->sl_lo = carry.l.lo;
     h->sh_hi = carry.h.hi;
     h->sh_lo = carry.h.lo;
-    const uint64_t ab = agg_base(off, t);
+    const uint64_t ab = agg_base(off, (uint32_t)t);
     if ((L & (kAggStride - 1)) == 0) B.agg_l[ab + L / kAggStride] = carry.l;
     if ((H & (kAggStride - 1)) == 0) B.agg_h[ab + H / kAggStride] = carry.h;
   }
@@ -1284,11 +1263,13 @@ int launch_build_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n1
   launch_setup(B, st);
   const uint32_t groups = (uint32_t)Lo.groups_max;
   hipLaunchKernelGGL(k_reduce_tile, dim3(tiles), dim3(kTileThreads), 0, st, B);
-  hipLaunchKernelGGL(k_reduce_group, dim3(groups), dim3(256), 0, st, B);
-  hipLaunchKernelGGL(k_finalize, dim3(B.T), dim3(256), 0, st, B);
+  const uint32_t gblocks = (groups + kWaveItemsPerBlock - 1) / kWaveItemsPerBlock;
+  const uint32_t tblocks = (B.T + kWaveItemsPerBlock - 1) / kWaveItemsPerBlock;
+  hipLaunchKernelGGL(k_reduce_group, dim3(gblocks), dim3(256), 0, st, B);
+  hipLaunchKernelGGL(k_finalize, dim3(tblocks), dim3(256), 0, st, B);
   hipLaunchKernelGGL(k_tilesum, dim3(tiles), dim3(kTileThreads), 0, st, B);
-  hipLaunchKernelGGL(k_scan_group, dim3(groups), dim3(kScanThreads), 0, st, B);
-  hipLaunchKernelGGL(k_scan_table, dim3(B.T), dim3(kScanThreads), 0, st, B);
+  hipLaunchKernelGGL(k_scan_group, dim3(gblocks), dim3(256), 0, st, B);
+  hipLaunchKernelGGL(k_scan_table, dim3(tblocks), dim3(256), 0, st, B);
   hipLaunchKernelGGL(k_partition, dim3(tiles), dim3(kPartThreads), 0, st, B);
   launch_split(B, st);
   // one block per section: P = 64 * waves threads, G = C / P rows per thread

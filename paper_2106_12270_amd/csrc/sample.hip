@@ -139,7 +139,7 @@ int launch_sample_rows(const TableRow *rows, uint64_t n, uint64_t count, uint64_
 // contiguous chunks so that a block's draws mostly fall in one table whose
 // rows stay in L2.
 // ---------------------------------------------------------------------------
-constexpr int kBatchPer = 4;  // draws per thread per chunk
+constexpr int kBatchPer = 8;  // draws per thread per chunk
 constexpr int kBatchChunk = kSampleThreads * kBatchPer;
 
 // largest t in [0, T) with start[t] <= x
@@ -156,6 +156,18 @@ __device__ __forceinline__ uint32_t find_first_le(const uint64_t *start, uint32_
 }
 
 template <bool kRows>
+__device__ __forceinline__ uint32_t batched_draw(const double *__restrict__ prob,
+                                                 const uint32_t *__restrict__ alias,
+                                                 const TableRow *__restrict__ rows, uint64_t base,
+                                                 uint64_t row, double coin) {
+  if (kRows) {
+    const TableRow r = rows[base + row];
+    return (coin < r.prob) ? (uint32_t)row : r.alias;
+  }
+  return (coin < prob[base + row]) ? (uint32_t)row : alias[base + row];
+}
+
+template <bool kRows>
 __global__ __launch_bounds__(kSampleThreads) void k_sample_batched(
     const double *__restrict__ prob, const uint32_t *__restrict__ alias,
     const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets,
@@ -168,44 +180,54 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_batched(
   }
   for (uint64_t c0 = (uint64_t)blockIdx.x * kBatchChunk; c0 < total_draws;
        c0 += (uint64_t)gridDim.x * kBatchChunk) {
-    uint32_t t = find_first_le(draw_off, T, c0);
-    uint64_t d[kBatchPer], row[kBatchPer], base[kBatchPer];
-    double coin[kBatchPer];
-    bool live[kBatchPer];
+    const uint64_t clast = (c0 + kBatchChunk < total_draws ? c0 + kBatchChunk : total_draws) - 1;
+    // the chunk's first and last tables (the same for every thread of the block)
+    const uint32_t tf = find_first_le(draw_off, T, c0);
+    const uint32_t tl = find_first_le(draw_off, T, clast);
+    if (tf == tl) {
+      // one table serves the whole chunk: its bounds are read once
+      const uint64_t a = offsets[tf], b = offsets[tf + 1], ds = draw_off[tf];
+      const uint64_t n = b - a;
+      const bool valid = !(b < a || b > total_items || n == 0 || n > 0xFFFFFFFFull || c0 < ds);
+      uint64_t row[kBatchPer];
+      double coin[kBatchPer];
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u) {
+        const uint64_t d = c0 + (uint64_t)u * kSampleThreads + threadIdx.x;
+        if (valid) draw_setup(d - ds, tf, k0, k1, n, row[u], coin[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kBatchPer; ++u) {
+        const uint64_t d = c0 + (uint64_t)u * kSampleThreads + threadIdx.x;
+        if (d > clast) continue;
+        if (valid) {
+          out[d] = batched_draw<kRows>(prob, alias, rows, a, row[u], coin[u]);
+        } else {
+          // an empty, oversized or out-of-range table gets no row reads
+          out[d] = 0xFFFFFFFFu;
+          *status = ALIAS_EINVAL;
+        }
+      }
+      continue;
+    }
+    // the chunk spans several tables: each draw finds its own
+    uint32_t t = tf;
 #pragma unroll
     for (int u = 0; u < kBatchPer; ++u) {
-      d[u] = c0 + (uint64_t)u * kSampleThreads + threadIdx.x;
-      live[u] = d[u] < total_draws;
-      while (t + 1 < T && draw_off[t + 1] <= d[u]) ++t;
+      const uint64_t d = c0 + (uint64_t)u * kSampleThreads + threadIdx.x;
+      if (d > clast) continue;
+      while (t + 1 < T && draw_off[t + 1] <= d) ++t;
       const uint64_t a = offsets[t], b = offsets[t + 1];
       const uint64_t n = b - a;
-      // an empty, oversized or out-of-range table gets no row reads
-      if (live[u] && (b < a || b > total_items || n == 0 || n > 0xFFFFFFFFull ||
-                      d[u] < draw_off[t])) {
-        out[d[u]] = 0xFFFFFFFFu;
+      if (b < a || b > total_items || n == 0 || n > 0xFFFFFFFFull || d < draw_off[t]) {
+        out[d] = 0xFFFFFFFFu;
         *status = ALIAS_EINVAL;
-        live[u] = false;
+        continue;
       }
-      base[u] = a;
-      if (live[u]) draw_setup(d[u] - draw_off[t], t, k0, k1, n, row[u], coin[u]);
-    }
-    if (kRows) {
-      TableRow r[kBatchPer];
-#pragma unroll
-      for (int u = 0; u < kBatchPer; ++u)
-        if (live[u]) r[u] = rows[base[u] + row[u]];
-#pragma unroll
-      for (int u = 0; u < kBatchPer; ++u)
-        if (live[u]) out[d[u]] = (coin[u] < r[u].prob) ? (uint32_t)row[u] : r[u].alias;
-    } else {
-      double p[kBatchPer];
-#pragma unroll
-      for (int u = 0; u < kBatchPer; ++u)
-        if (live[u]) p[u] = prob[base[u] + row[u]];
-#pragma unroll
-      for (int u = 0; u < kBatchPer; ++u)
-        if (live[u])
-          out[d[u]] = (coin[u] < p[u]) ? (uint32_t)row[u] : alias[base[u] + row[u]];
+      uint64_t row;
+      double coin;
+      draw_setup(d - draw_off[t], t, k0, k1, n, row, coin);
+      out[d] = batched_draw<kRows>(prob, alias, rows, a, row, coin);
     }
   }
 }

@@ -1,0 +1,597 @@
+// Batched sectioned sampling: every table of a batch sampled section by
+// section (arXiv 2106.12270, Sec. 5, the sectioned methods), in one fixed
+// sequence of launches with no host readback (so it can be captured into a
+// HIP graph together with the batched build).
+//
+// Table t owns rows [offsets[t], offsets[t+1]) and output positions
+// [draw_off[t], draw_off[t+1]).  It gets exactly the draws that single-table
+// sectioned sampling writes for it alone with table id t: its
+// c_t = draw_off[t+1] - draw_off[t] draws grouped by section of R = 2^log2r
+// rows, the per-section counts taken from c_t virtual draws (two per Philox
+// block with counter (b lo, b hi, t, 1)), section s's draw j made from the
+// block with counter (j lo, j hi, t, 2 + 4 s).
+//
+// The sections of all tables are numbered globally, table by table (table
+// t's sections start at sec_start[t]).  Since table t's section counts add
+// up to c_t, the exclusive prefix of all counts in that order is each
+// section's output offset, and table t's sections fill exactly its output
+// range.  A table with draws but no usable rows (empty, or more than
+// 2^32 - 1) gets one placeholder section holding all its draws, written as
+// 0xFFFFFFFF.
+//
+//   k_bs_init         clears the header (totals, flags)
+//   k_bs_scan_*       three-phase exclusive scan (block sums, one block over
+//                     the sums, block prefixes): first over the tables
+//                     (sections and virtual-draw pairs per table ->
+//                     sec_start, pair_start, the checks), then over the
+//                     sections (counts -> output offsets)
+//   k_bs_zero         clears the per-section counts
+//   k_bs_count        all tables' virtual draws -> per-section counts; a
+//                     block takes a contiguous range of pairs and counts in
+//                     an LDS histogram over the sections that range can hit
+//   k_bs_draw         output chunks of 4096 positions; a position belongs
+//                     to the section whose output range holds it, and gets
+//                     that section's draw j = position - section offset (a
+//                     chunk spanning several sections stages their
+//                     descriptions in LDS)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "alias_mi355x.h"
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace amdalias {
+
+constexpr int kBsThreads = 256;          // count and draw kernels
+constexpr int kBsPer = 16;               // output positions per thread per chunk
+constexpr uint64_t kBsChunk = (uint64_t)kBsThreads * kBsPer;
+constexpr uint32_t kBsHist = 4096;       // sections a count block histograms in LDS
+constexpr int kBsScanThreads = 1024;     // scan kernels
+constexpr int kBsScanPer = 4;            // consecutive items per scan thread
+constexpr uint64_t kBsScanBlock = (uint64_t)kBsScanThreads * kBsScanPer;
+constexpr uint32_t kBsBadTable = 1u;     // a table with draws has no usable rows
+constexpr uint32_t kBsBadOffsets = 2u;   // offsets or draw offsets inconsistent
+
+struct BsHeader {
+  uint64_t sections;  // S: sections of all tables
+  uint64_t pairs;     // virtual-draw pairs of all tables
+  uint32_t flags;     // kBsBadTable | kBsBadOffsets
+  uint32_t pad;
+};
+
+struct Two {
+  uint64_t a, b;
+};
+
+struct BsLayout {
+  uint64_t sec_start, pair_start, bsum, bpre, counts, sec_off, total;
+  uint64_t S_max, nb_max;
+};
+
+inline bool bs_layout(uint32_t T, uint64_t total_items, uint64_t total_draws, uint32_t log2r,
+                      BsLayout *L) {
+  if (T == 0 || T > kMaxTables || total_items == 0 || total_items > (1ull << 40) ||
+      total_draws > (1ull << 40) || log2r < 6 || log2r > 31)
+    return false;
+  // table t has at most ceil(n_t / R) <= n_t / R + 1 sections
+  L->S_max = ((total_items + (1ull << log2r) - 1) >> log2r) + T;
+  if (L->S_max > 0xFFFFFFFFull) return false;
+  const uint64_t nbt = (T + kBsScanBlock - 1) / kBsScanBlock;
+  const uint64_t nbs = (L->S_max + kBsScanBlock - 1) / kBsScanBlock;
+  L->nb_max = nbt > nbs ? nbt : nbs;
+  uint64_t off = 256;  // the header
+  auto take = [&](uint64_t b) {
+    const uint64_t at = off;
+    off = align256(off + b);
+    return at;
+  };
+  L->sec_start = take((uint64_t)(T + 1) * 8);
+  L->pair_start = take((uint64_t)(T + 1) * 8);
+  L->bsum = take(L->nb_max * sizeof(Two));
+  L->bpre = take(L->nb_max * sizeof(Two));
+  L->counts = take(L->S_max * 8);
+  L->sec_off = take((L->S_max + 1) * 8);
+  L->total = off;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Per-table classification
+// ---------------------------------------------------------------------------
+struct BsTable {
+  uint64_t a, n, c;  // first row, rows, draws
+  int kind;          // 0 usable, 1 no usable rows, 2 ranges outside the batch
+};
+
+__device__ __forceinline__ BsTable bs_table(const uint64_t *__restrict__ offsets,
+                                            const uint64_t *__restrict__ draw_off, uint64_t t,
+                                            uint64_t total_items, uint64_t total_draws) {
+  BsTable r;
+  const uint64_t a = offsets[t], b = offsets[t + 1];
+  const uint64_t da = draw_off[t], db = draw_off[t + 1];
+  r.a = a;
+  r.n = b - a;
+  r.c = db - da;
+  if (b < a || b > total_items || db < da || db > total_draws)
+    r.kind = 2;
+  else if (r.n == 0 || r.n > 0xFFFFFFFFull)
+    r.kind = 1;
+  else
+    r.kind = 0;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Three-phase exclusive scan of a pair of u64 sequences
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Two block_excl2(Two v, Two *s_w, Two *tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t a = v.a, b = v.b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t oa = __shfl_up(a, d, 64), ob = __shfl_up(b, d, 64);
+    if (lane >= d) {
+      a += oa;
+      b += ob;
+    }
+  }
+  if (lane == 63) s_w[wave] = Two{a, b};
+  __syncthreads();
+  Two pre{0, 0}, t{0, 0};
+#pragma unroll
+  for (int k = 0; k < kBsScanThreads / 64; ++k) {
+    const Two w = s_w[k];
+    if (k < wave) {
+      pre.a += w.a;
+      pre.b += w.b;
+    }
+    t.a += w.a;
+    t.b += w.b;
+  }
+  __syncthreads();
+  *tot = t;
+  return Two{pre.a + a - v.a, pre.b + b - v.b};
+}
+
+// Sources: size() items, value(i) the pair at item i.  Sinks: put(i, ex)
+// the exclusive prefix at item i, total(tot) after the last item.
+struct TableSrc {
+  const uint64_t *offsets, *draw_off;
+  uint64_t T, total_items, total_draws;
+  uint32_t log2r;
+  BsHeader *h;
+  uint64_t *sec_start, *pair_start;
+  __device__ uint64_t size() const { return T; }
+  __device__ Two value(uint64_t t) const {
+    const BsTable q = bs_table(offsets, draw_off, t, total_items, total_draws);
+    if (q.kind == 0) return Two{(q.n + (1ull << log2r) - 1) >> log2r, (q.c + 1) / 2};
+    if (q.kind == 1) return Two{q.c ? 1ull : 0ull, 0};
+    return Two{0, 0};
+  }
+  __device__ uint32_t flags(uint64_t t) const {
+    const BsTable q = bs_table(offsets, draw_off, t, total_items, total_draws);
+    if (q.kind == 2) return kBsBadOffsets;
+    if (t == 0 && (offsets[0] != 0 || draw_off[0] != 0)) return kBsBadOffsets;
+    if (t == T - 1 && (offsets[T] != total_items || draw_off[T] != total_draws))
+      return kBsBadOffsets;
+    return (q.kind == 1 && q.c) ? kBsBadTable : 0u;
+  }
+  __device__ void put(uint64_t t, Two ex) const {
+    sec_start[t] = ex.a;
+    pair_start[t] = ex.b;
+  }
+  __device__ void total(Two s) const {
+    sec_start[T] = s.a;
+    pair_start[T] = s.b;
+    h->sections = s.a;
+    h->pairs = s.b;
+  }
+};
+
+struct SectionSrc {
+  const uint64_t *counts;
+  const BsHeader *h;
+  uint64_t *sec_off;
+  __device__ uint64_t size() const { return h->sections; }
+  __device__ Two value(uint64_t s) const { return Two{counts[s], 0}; }
+  __device__ uint32_t flags(uint64_t) const { return 0u; }
+  __device__ void put(uint64_t s, Two ex) const { sec_off[s] = ex.a; }
+  __device__ void total(Two s) const { sec_off[h->sections] = s.a; }
+};
+
+// this thread's kBsScanPer consecutive items of block `blk` and their sum
+template <class Src>
+__device__ __forceinline__ Two scan_items(const Src &src, uint64_t blk, uint64_t N, Two *v,
+                                          uint32_t *fl) {
+  Two s{0, 0};
+  const uint64_t i0 = blk * kBsScanBlock + (uint64_t)threadIdx.x * kBsScanPer;
+#pragma unroll
+  for (int u = 0; u < kBsScanPer; ++u) {
+    v[u] = Two{0, 0};
+    if (i0 + u < N) {
+      v[u] = src.value(i0 + u);
+      *fl |= src.flags(i0 + u);
+    }
+    s.a += v[u].a;
+    s.b += v[u].b;
+  }
+  return s;
+}
+
+template <class Src>
+__global__ __launch_bounds__(kBsScanThreads) void k_bs_scan_reduce(Src src, Two *bsum,
+                                                                   BsHeader *h) {
+  __shared__ Two s_w[kBsScanThreads / 64];
+  const uint64_t N = src.size();
+  const uint64_t nb = (N + kBsScanBlock - 1) / kBsScanBlock;
+  if (blockIdx.x >= nb) return;  // uniform over the block
+  Two v[kBsScanPer];
+  uint32_t fl = 0;
+  const Two s = scan_items(src, blockIdx.x, N, v, &fl);
+  Two tot;
+  block_excl2(s, s_w, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  if (fl) atomicOr(&h->flags, fl);
+}
+
+// one block: exclusive prefix of the block sums, the totals, the status
+template <class Src>
+__global__ __launch_bounds__(kBsScanThreads) void k_bs_scan_top(Src src, const Two *bsum,
+                                                                Two *bpre, BsHeader *h,
+                                                                int32_t *status) {
+  __shared__ Two s_w[kBsScanThreads / 64];
+  const uint64_t N = src.size();
+  const uint64_t nb = (N + kBsScanBlock - 1) / kBsScanBlock;
+  Two carry{0, 0};
+  for (uint64_t base = 0; base < nb; base += kBsScanThreads) {
+    const uint64_t i = base + threadIdx.x;
+    const Two v = i < nb ? bsum[i] : Two{0, 0};
+    Two tot;
+    const Two ex = block_excl2(v, s_w, &tot);
+    if (i < nb) bpre[i] = Two{carry.a + ex.a, carry.b + ex.b};
+    carry.a += tot.a;
+    carry.b += tot.b;
+  }
+  if (threadIdx.x == 0) {
+    src.total(carry);
+    if (status) *status = h->flags ? ALIAS_EINVAL : ALIAS_OK;
+  }
+}
+
+template <class Src>
+__global__ __launch_bounds__(kBsScanThreads) void k_bs_scan_down(Src src, const Two *bpre) {
+  __shared__ Two s_w[kBsScanThreads / 64];
+  const uint64_t N = src.size();
+  const uint64_t nb = (N + kBsScanBlock - 1) / kBsScanBlock;
+  if (blockIdx.x >= nb) return;
+  Two v[kBsScanPer];
+  uint32_t fl = 0;
+  const Two s = scan_items(src, blockIdx.x, N, v, &fl);
+  Two tot;
+  Two ex = block_excl2(s, s_w, &tot);
+  const Two bp = bpre[blockIdx.x];
+  ex.a += bp.a;
+  ex.b += bp.b;
+  const uint64_t i0 = blockIdx.x * kBsScanBlock + (uint64_t)threadIdx.x * kBsScanPer;
+#pragma unroll
+  for (int u = 0; u < kBsScanPer; ++u) {
+    if (i0 + u < N) src.put(i0 + u, ex);
+    ex.a += v[u].a;
+    ex.b += v[u].b;
+  }
+}
+
+__global__ void k_bs_init(BsHeader *h) {
+  if (threadIdx.x == 0) {
+    h->sections = 0;
+    h->pairs = 0;
+    h->flags = 0;
+    h->pad = 0;
+  }
+}
+
+__global__ void k_bs_zero(uint64_t *counts, const BsHeader *h) {
+  const uint64_t S = h->sections;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    counts[i] = 0;
+}
+
+// largest i in [lo, hi) with start[i] <= x (start[lo] <= x)
+__device__ __forceinline__ uint64_t find_le(const uint64_t *start, uint64_t lo, uint64_t hi,
+                                            uint64_t x) {
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (start[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Counts
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBsThreads) void k_bs_count(
+    const uint64_t *__restrict__ offsets, const uint64_t *__restrict__ draw_off, uint32_t T,
+    uint64_t total_items, uint64_t total_draws, uint32_t log2r,
+    const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ pair_start,
+    const BsHeader *h, uint32_t k0, uint32_t k1, unsigned long long *counts) {
+  __shared__ uint32_t hist[kBsHist];
+  if (h->flags & kBsBadOffsets) return;  // nothing is counted (uniform)
+  // placeholder sections: all draws of a table without usable rows
+  for (uint64_t t = (uint64_t)blockIdx.x * kBsThreads + threadIdx.x; t < T;
+       t += (uint64_t)gridDim.x * kBsThreads) {
+    const BsTable q = bs_table(offsets, draw_off, t, total_items, total_draws);
+    if (q.kind == 1 && q.c) atomicAdd(&counts[sec_start[t]], (unsigned long long)q.c);
+  }
+  const uint64_t P = h->pairs;
+  uint64_t per = (P + gridDim.x - 1) / gridDim.x;
+  per = (per + kBsThreads - 1) / kBsThreads * kBsThreads;
+  const uint64_t g0 = (uint64_t)blockIdx.x * per;
+  const uint64_t g1 = g0 + per < P ? g0 + per : P;
+  if (g0 >= g1) return;  // uniform over the block
+  const uint64_t tf = find_le(pair_start, 0, T, g0), tl = find_le(pair_start, tf, T, g1 - 1);
+  const uint64_t sbase = sec_start[tf];
+  const uint64_t span = sec_start[tl + 1] - sbase;
+  const bool lds = span <= kBsHist;
+  if (lds)
+    for (uint64_t i = threadIdx.x; i < span; i += kBsThreads) hist[i] = 0;
+  __syncthreads();
+  uint64_t t = tf;
+  uint64_t ps = pair_start[t], pe = pair_start[t + 1];
+  uint64_t n = offsets[t + 1] - offsets[t], c = draw_off[t + 1] - draw_off[t], ss = sec_start[t];
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += kBsThreads) {
+    if (g >= pe) {
+      // g < P = pair_start[T], so the table holding g is found before T
+      t = find_le(pair_start, t + 1, tl + 1, g);
+      ps = pair_start[t];
+      pe = pair_start[t + 1];
+      n = offsets[t + 1] - offsets[t];
+      c = draw_off[t + 1] - draw_off[t];
+      ss = sec_start[t];
+    }
+    const uint64_t b = g - ps;
+    u32x4 cc;
+    cc.x = (uint32_t)b;
+    cc.y = (uint32_t)(b >> 32);
+    cc.z = (uint32_t)t;
+    cc.w = 1u;
+    const u32x4 r = philox4x32_10(cc, k0, k1);
+    const uint64_t x0 = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    const uint64_t x1 = (uint64_t)r.z | ((uint64_t)r.w << 32);
+    const uint64_t s0 = ss + (__umul64hi(x0, n) >> log2r);
+    const uint64_t s1 = ss + (__umul64hi(x1, n) >> log2r);
+    const bool two = 2 * b + 1 < c;
+    if (lds) {
+      atomicAdd(&hist[s0 - sbase], 1u);
+      if (two) atomicAdd(&hist[s1 - sbase], 1u);
+    } else {
+      atomicAdd(&counts[s0], 1ull);
+      if (two) atomicAdd(&counts[s1], 1ull);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (uint64_t i = threadIdx.x; i < span; i += kBsThreads)
+      if (hist[i]) atomicAdd(&counts[sbase + i], (unsigned long long)hist[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Draws
+// ---------------------------------------------------------------------------
+struct BsSec {
+  uint64_t a, base, Rs, so;  // table's first row, section's first row and rows, output offset
+  uint32_t t, w;             // table, Philox word 2 + 4 s
+  bool ok;                   // the table has usable rows
+};
+
+__device__ __forceinline__ BsSec bs_section(const uint64_t *__restrict__ offsets,
+                                            const uint64_t *__restrict__ sec_start,
+                                            const uint64_t *__restrict__ sec_off, uint64_t s,
+                                            uint64_t t, uint32_t log2r) {
+  BsSec q;
+  const uint64_t a = offsets[t], n = offsets[t + 1] - a;
+  const uint64_t ls = s - sec_start[t];
+  q.a = a;
+  q.ok = n != 0 && n <= 0xFFFFFFFFull;
+  q.base = ls << log2r;
+  q.Rs = q.ok ? (n - q.base < (1ull << log2r) ? n - q.base : (1ull << log2r)) : 0;
+  q.so = sec_off[s];
+  q.t = (uint32_t)t;
+  q.w = 2u + 4u * (uint32_t)ls;
+  return q;
+}
+
+__device__ __forceinline__ void bs_setup(const BsSec &q, uint64_t j, uint32_t k0, uint32_t k1,
+                                         uint64_t &row, double &coin) {
+  u32x4 cc;
+  cc.x = (uint32_t)j;
+  cc.y = (uint32_t)(j >> 32);
+  cc.z = q.t;
+  cc.w = q.w;
+  const u32x4 r = philox4x32_10(cc, k0, k1);
+  const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
+  row = q.base + __umul64hi(x, q.Rs);
+  const uint64_t u = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
+  coin = (double)u * 0x1p-53;
+}
+
+template <bool kRows>
+__device__ __forceinline__ uint32_t bs_pick(const double *__restrict__ prob,
+                                            const uint32_t *__restrict__ alias,
+                                            const TableRow *__restrict__ rows, uint64_t a,
+                                            uint64_t row, double coin) {
+  if (kRows) {
+    const TableRow r = rows[a + row];
+    return (coin < r.prob) ? (uint32_t)row : r.alias;
+  }
+  return (coin < prob[a + row]) ? (uint32_t)row : alias[a + row];
+}
+
+// Chunks are dealt to eight block classes (block b % 8 runs on one XCD under
+// round-robin dispatch): class c takes the c-th eighth of the output, in
+// order, so the sections in flight on an XCD are few and neighbouring and
+// their rows stay in that XCD's L2.
+template <bool kRows>
+__global__ __launch_bounds__(kBsThreads) void k_bs_draw(
+    const double *__restrict__ prob, const uint32_t *__restrict__ alias,
+    const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t T,
+    uint32_t log2r, const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
+    const BsHeader *h, uint64_t total_draws, uint32_t k0, uint32_t k1, uint32_t *__restrict__ out) {
+  __shared__ BsSec s_q[kBsThreads];
+  const uint64_t S = h->sections;
+  const bool bad = (h->flags & kBsBadOffsets) != 0;
+  const uint64_t C = (total_draws + kBsChunk - 1) / kBsChunk;
+  const uint64_t Rg = (C + 7) / 8;
+  const uint64_t cls = blockIdx.x % 8, nb = gridDim.x / 8;
+  const uint64_t cend = (cls + 1) * Rg < C ? (cls + 1) * Rg : C;
+  for (uint64_t ch = cls * Rg + blockIdx.x / 8; ch < cend; ch += nb) {
+    const uint64_t o0 = ch * kBsChunk;
+    const uint64_t olast = (o0 + kBsChunk < total_draws ? o0 + kBsChunk : total_draws) - 1;
+    if (bad) {
+      for (uint64_t o = o0 + threadIdx.x; o <= olast; o += kBsThreads) out[o] = 0xFFFFFFFFu;
+      continue;
+    }
+    // consistent offsets: the sections' output ranges tile [0, total_draws)
+    const uint64_t sf = find_le(sec_off, 0, S, o0), sl = find_le(sec_off, sf, S, olast);
+    const uint64_t tf = find_le(sec_start, 0, T, sf);
+    if (sf == sl) {
+      // one section serves the whole chunk
+      const BsSec q = bs_section(offsets, sec_start, sec_off, sf, tf, log2r);
+      uint64_t row[kBsPer];
+      double coin[kBsPer];
+#pragma unroll
+      for (int u = 0; u < kBsPer; ++u) {
+        const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
+        bs_setup(q, o - q.so, k0, k1, row[u], coin[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kBsPer; ++u) {
+        const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
+        if (o > olast) continue;
+        out[o] = q.ok ? bs_pick<kRows>(prob, alias, rows, q.a, row[u], coin[u]) : 0xFFFFFFFFu;
+      }
+      continue;
+    }
+    const uint64_t tl = find_le(sec_start, tf, T, sl);
+    const uint64_t m = sl - sf + 1;
+    if (m <= kBsThreads) {
+      // several sections, at most one per thread: their descriptions are
+      // staged in LDS and each position finds its section there
+      if (threadIdx.x < m) {
+        const uint64_t s = sf + threadIdx.x;
+        s_q[threadIdx.x] = bs_section(offsets, sec_start, sec_off, s,
+                                      find_le(sec_start, tf, tl + 1, s), log2r);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int u = 0; u < kBsPer; ++u) {
+        const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
+        if (o > olast) break;
+        uint32_t lo = 0, hi = (uint32_t)m;  // largest i with s_q[i].so <= o
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (s_q[mid].so <= o)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const BsSec q = s_q[lo];
+        uint64_t row;
+        double coin;
+        bs_setup(q, o - q.so, k0, k1, row, coin);
+        out[o] = q.ok ? bs_pick<kRows>(prob, alias, rows, q.a, row, coin) : 0xFFFFFFFFu;
+      }
+      __syncthreads();  // s_q is rewritten for the next chunk
+      continue;
+    }
+    // more sections than threads: each position finds its own in global
+    // memory (positions rise per thread)
+    uint64_t s = sf, t = tf;
+#pragma unroll 4
+    for (int u = 0; u < kBsPer; ++u) {
+      const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
+      if (o > olast) break;
+      s = find_le(sec_off, s, sl + 1, o);
+      t = find_le(sec_start, t, tl + 1, s);
+      const BsSec q = bs_section(offsets, sec_start, sec_off, s, t, log2r);
+      uint64_t row;
+      double coin;
+      bs_setup(q, o - q.so, k0, k1, row, coin);
+      out[o] = q.ok ? bs_pick<kRows>(prob, alias, rows, q.a, row, coin) : 0xFFFFFFFFu;
+    }
+  }
+}
+
+size_t bs_workspace_bytes(uint32_t T, uint64_t total_items, uint64_t total_draws,
+                          uint32_t log2r) {
+  BsLayout L;
+  if (!bs_layout(T, total_items, total_draws, log2r, &L)) return 0;
+  return (size_t)L.total;
+}
+
+int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
+                                    const TableRow *rows, const uint64_t *offsets,
+                                    const uint64_t *draw_off, uint32_t T, uint64_t total_items,
+                                    uint64_t total_draws, uint64_t seed, uint32_t log2r,
+                                    uint32_t *out, void *d_ws, size_t ws_bytes, int32_t *status,
+                                    uint32_t draw_blocks, hipStream_t st) {
+  BsLayout L;
+  if (!bs_layout(T, total_items, total_draws, log2r, &L)) return ALIAS_EINVAL;
+  if (ws_bytes < L.total) return ALIAS_EWORKSPACE;
+  char *ws = (char *)d_ws;
+  BsHeader *h = (BsHeader *)ws;
+  uint64_t *sec_start = (uint64_t *)(ws + L.sec_start), *pair_start = (uint64_t *)(ws + L.pair_start);
+  Two *bsum = (Two *)(ws + L.bsum), *bpre = (Two *)(ws + L.bpre);
+  uint64_t *counts = (uint64_t *)(ws + L.counts), *sec_off = (uint64_t *)(ws + L.sec_off);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+
+  hipLaunchKernelGGL(k_bs_init, dim3(1), dim3(64), 0, st, h);
+  const TableSrc ts{offsets, draw_off, T, total_items, total_draws, log2r, h, sec_start, pair_start};
+  const uint32_t nbt = (uint32_t)((T + kBsScanBlock - 1) / kBsScanBlock);
+  hipLaunchKernelGGL(k_bs_scan_reduce<TableSrc>, dim3(nbt), dim3(kBsScanThreads), 0, st, ts, bsum,
+                     h);
+  hipLaunchKernelGGL(k_bs_scan_top<TableSrc>, dim3(1), dim3(kBsScanThreads), 0, st, ts,
+                     (const Two *)bsum, bpre, h, status);
+  hipLaunchKernelGGL(k_bs_scan_down<TableSrc>, dim3(nbt), dim3(kBsScanThreads), 0, st, ts,
+                     (const Two *)bpre);
+  uint64_t zb = (L.S_max + 255) / 256;
+  if (zb > 4096) zb = 4096;
+  hipLaunchKernelGGL(k_bs_zero, dim3((uint32_t)zb), dim3(256), 0, st, counts, (const BsHeader *)h);
+  // pairs <= total_draws / 2 + T; about 16 pairs per thread, at most 2048 blocks
+  uint64_t cb = (total_draws / 2 + T + kBsThreads * 16 - 1) / (kBsThreads * 16);
+  if (cb > 2048) cb = 2048;
+  if (cb == 0) cb = 1;
+  hipLaunchKernelGGL(k_bs_count, dim3((uint32_t)cb), dim3(kBsThreads), 0, st, offsets, draw_off, T,
+                     total_items, total_draws, log2r, (const uint64_t *)sec_start,
+                     (const uint64_t *)pair_start, (const BsHeader *)h, k0, k1,
+                     (unsigned long long *)counts);
+  const SectionSrc ss{(const uint64_t *)counts, h, sec_off};
+  const uint32_t nbs = (uint32_t)((L.S_max + kBsScanBlock - 1) / kBsScanBlock);
+  hipLaunchKernelGGL(k_bs_scan_reduce<SectionSrc>, dim3(nbs), dim3(kBsScanThreads), 0, st, ss,
+                     bsum, h);
+  hipLaunchKernelGGL(k_bs_scan_top<SectionSrc>, dim3(1), dim3(kBsScanThreads), 0, st, ss,
+                     (const Two *)bsum, bpre, h, (int32_t *)nullptr);
+  hipLaunchKernelGGL(k_bs_scan_down<SectionSrc>, dim3(nbs), dim3(kBsScanThreads), 0, st, ss,
+                     (const Two *)bpre);
+  uint64_t db = draw_blocks ? draw_blocks : 256;
+  const uint64_t chunks = (total_draws + kBsChunk - 1) / kBsChunk;
+  if (db > chunks) db = chunks;
+  db = (db + 7) / 8 * 8;  // eight block classes
+  if (db == 0) db = 8;
+  if (rows)
+    hipLaunchKernelGGL(k_bs_draw<true>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, nullptr,
+                       nullptr, rows, offsets, T, log2r, (const uint64_t *)sec_start,
+                       (const uint64_t *)sec_off, (const BsHeader *)h, total_draws, k0, k1, out);
+  else
+    hipLaunchKernelGGL(k_bs_draw<false>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, prob, alias,
+                       nullptr, offsets, T, log2r, (const uint64_t *)sec_start,
+                       (const uint64_t *)sec_off, (const BsHeader *)h, total_draws, k0, k1, out);
+  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+}  // namespace amdalias
