@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SECTION_LOG2R_BATCH = 13  # rows per section of batched sectioned sampling: 2^13
+SECTION_LOG2R_BATCH = 12  # rows per section of batched sectioned sampling: 2^12
 # algorithmic bytes of the build per item: read w twice (16: total weight,
 # then partition), write the light/heavy lists with weights (12), read them in
 # the pack (12), write the table row (8 + 4)
@@ -263,7 +263,7 @@ def batched(pkg, inputs, name, per_table_loop=False, learned=False, reps=5, epoc
     out["graph_ms"] = round(timed(g.replay, reps), 4)
     del g
     # batched sectioned sampling (Sec. 5 sectioned methods over the batch):
-    # the same draw counts, grouped by table section of 2^13 rows
+    # the same draw counts, grouped by table section of 2^12 rows
     bs = pkg.BatchedSectionedSampler(T, total, nd, SECTION_LOG2R_BATCH, device=dev)
 
     def sec():

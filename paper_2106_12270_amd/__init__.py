@@ -672,7 +672,7 @@ class BatchedSectionedSampler:
     rows (see the C header).  Table t's output range holds exactly what
     SectionedSampler gives for that table alone with table_id t."""
 
-    def __init__(self, T, total_items, total_draws, log2r=13, device="cuda"):
+    def __init__(self, T, total_items, total_draws, log2r=12, device="cuda"):
         import torch
 
         self.T, self.total_items = int(T), int(total_items)

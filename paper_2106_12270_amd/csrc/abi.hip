@@ -28,6 +28,7 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
                                     const uint64_t *draw_off, uint32_t T, uint64_t total_items,
                                     uint64_t total_draws, uint64_t seed, uint32_t log2r,
                                     uint32_t *out, void *d_ws, size_t ws_bytes, int32_t *status,
+                                    uint32_t table_base, uint64_t *counts_out,
                                     uint32_t draw_blocks, hipStream_t st);
 int launch_sample_sectioned(const double *prob, const uint32_t *alias, const TableRow *rows,
                             uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
@@ -296,7 +297,7 @@ int alias_sample_batched_sectioned(const double *d_prob, const uint32_t *d_alias
   if (st) return st;
   return launch_sample_batched_sectioned(d_prob, d_alias, nullptr, d_offsets, d_draw_offsets, T,
                                          total_items, total_draws, seed, log2r, d_out, d_ws,
-                                         ws_bytes, d_status, 0, (hipStream_t)stream);
+                                         ws_bytes, d_status, 0, nullptr, 0, (hipStream_t)stream);
 }
 
 int alias_sample_batched_sectioned_rows(const void *d_rows, const uint64_t *d_offsets, uint32_t T,
@@ -310,7 +311,8 @@ int alias_sample_batched_sectioned_rows(const void *d_rows, const uint64_t *d_of
   if (st) return st;
   return launch_sample_batched_sectioned(nullptr, nullptr, (const TableRow *)d_rows, d_offsets,
                                          d_draw_offsets, T, total_items, total_draws, seed, log2r,
-                                         d_out, d_ws, ws_bytes, d_status, 0, (hipStream_t)stream);
+                                         d_out, d_ws, ws_bytes, d_status, 0, nullptr, 0,
+                                         (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -256,263 +256,4 @@ int launch_sample_batched(const double *prob, const uint32_t *alias, const Table
 }
 
 
-// ---------------------------------------------------------------------------
-// Sectioned sampling (Sec. 5: many draws served from one cached section of
-// the table), with exact per-section counts.  Rows are grouped into
-// S = ceil(n / R) sections of R = 2^log2r rows.
-//   k_sec_count  the counts: `count` virtual draws, two per Philox block
-//                (counter (b lo, b hi, table, 1)), each picking a row exactly
-//                as a plain draw does; c_s = virtual draws landing in
-//                section s (integer sums: any order gives the same counts);
-//   k_sec_scan   exclusive prefix of the counts (output offsets) and of the
-//                per-section numbers of work items of kSecItem draws;
-//   k_sec_draw   work items: section s's draws j with counter
-//                (j lo, j hi, table, 2 + 4 s), row = s R + floor(x R_s / 2^64),
-//                the coin as a plain draw, written to out[C_s + j].  All draws
-//                of a section read rows of one R-row range, which stays in L2.
-// ---------------------------------------------------------------------------
-constexpr int kSecThreads = 256;
-constexpr uint32_t kSecItem = 8192;       // draws per work item
-constexpr uint32_t kSecLdsHist = 16384;   // sections counted in LDS (else in global memory)
-
-struct SecLayout {
-  uint64_t counts, offsets, work, total;  // byte offsets in the workspace
-  uint64_t S;
-};
-
-inline bool sec_layout(uint64_t n, uint64_t count, uint32_t log2r, SecLayout *L) {
-  if (n == 0 || n > 0xFFFFFFFFull || log2r < 6 || log2r > 31 || count > (1ull << 40))
-    return false;
-  const uint64_t R = 1ull << log2r;
-  L->S = (n + R - 1) / R;
-  if (L->S > (1ull << 20)) return false;
-  uint64_t off = 0;
-  auto take = [&](uint64_t b) {
-    uint64_t at = off;
-    off = align256(off + b);
-    return at;
-  };
-  L->counts = take(L->S * 8);
-  L->offsets = take((L->S + 1) * 8);
-  L->work = take((8 * ((L->S + 7) / 8) + 1) * 8);
-  L->total = off;
-  return true;
-}
-
-__global__ void k_sec_zero(uint64_t *c, uint64_t S) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < S) c[i] = 0;
-}
-
-__global__ __launch_bounds__(kSecThreads) void k_sec_count(uint64_t n, uint64_t count,
-                                                           uint32_t log2r, uint64_t S,
-                                                           uint32_t k0, uint32_t k1,
-                                                           uint32_t table,
-                                                           unsigned long long *counts) {
-  __shared__ uint32_t hist[kSecLdsHist];
-  const bool lds = S <= kSecLdsHist;
-  if (lds)
-    for (uint64_t i = threadIdx.x; i < S; i += kSecThreads) hist[i] = 0;
-  __syncthreads();
-  const uint64_t pairs = (count + 1) / 2;
-  const uint64_t G = (uint64_t)gridDim.x * kSecThreads;
-  for (uint64_t b = (uint64_t)blockIdx.x * kSecThreads + threadIdx.x; b < pairs; b += G) {
-    u32x4 c;
-    c.x = (uint32_t)b;
-    c.y = (uint32_t)(b >> 32);
-    c.z = table;
-    c.w = 1u;
-    const u32x4 r = philox4x32_10(c, k0, k1);
-    const uint64_t x0 = (uint64_t)r.x | ((uint64_t)r.y << 32);
-    const uint64_t x1 = (uint64_t)r.z | ((uint64_t)r.w << 32);
-    const uint64_t s0 = __umul64hi(x0, n) >> log2r;
-    const bool two = 2 * b + 1 < count;
-    const uint64_t s1 = __umul64hi(x1, n) >> log2r;
-    if (lds) {
-      atomicAdd(&hist[s0], 1u);
-      if (two) atomicAdd(&hist[s1], 1u);
-    } else {
-      atomicAdd(&counts[s0], 1ull);
-      if (two) atomicAdd(&counts[s1], 1ull);
-    }
-  }
-  if (lds) {
-    __syncthreads();
-    for (uint64_t i = threadIdx.x; i < S; i += kSecThreads)
-      if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
-  }
-}
-
-// Sections are served per XCD class: blocks b with b % 8 == c (the
-// round-robin dispatch puts them on one XCD) take the work items of the
-// sections s with s % 8 == c, so the sections in flight on an XCD stay few
-// and their rows stay in that XCD's L2.  Permuted section order: position
-// p = c * Sc + k holds section s = 8 k + c (Sc = ceil(S / 8); s >= S is
-// empty).
-__device__ __forceinline__ uint64_t sec_at(uint64_t p, uint64_t Sc) {
-  return (p % Sc) * 8 + p / Sc;
-}
-
-__device__ __forceinline__ uint64_t block_excl_u64(uint64_t v, uint64_t *s_w, uint64_t *tot) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint64_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t o = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += o;
-  }
-  if (lane == 63) s_w[wave] = inc;
-  __syncthreads();
-  uint64_t pre = 0, t = 0;
-  for (int k = 0; k < 16; ++k) {
-    if (k < wave) pre += s_w[k];
-    t += s_w[k];
-  }
-  __syncthreads();
-  *tot = t;
-  return pre + inc - v;
-}
-
-// one block: exclusive prefix of the counts in section order -> offsets[0..S];
-// of the work items in the permuted order -> work[0..8 Sc]
-__global__ __launch_bounds__(1024) void k_sec_scan(const uint64_t *counts, uint64_t S,
-                                                   uint64_t *offsets, uint64_t *work) {
-  __shared__ uint64_t s_w[16];
-  uint64_t carry = 0;
-  for (uint64_t base = 0; base < S; base += 1024) {
-    const uint64_t i = base + threadIdx.x;
-    const uint64_t c = i < S ? counts[i] : 0;
-    uint64_t tot;
-    const uint64_t ex = block_excl_u64(c, s_w, &tot);
-    if (i < S) offsets[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) offsets[S] = carry;
-  const uint64_t Sc = (S + 7) / 8, P = 8 * Sc;
-  carry = 0;
-  for (uint64_t base = 0; base < P; base += 1024) {
-    const uint64_t p = base + threadIdx.x;
-    uint64_t wi = 0;
-    if (p < P) {
-      const uint64_t sec = sec_at(p, Sc);
-      if (sec < S) wi = (counts[sec] + kSecItem - 1) / kSecItem;
-    }
-    uint64_t tot;
-    const uint64_t ex = block_excl_u64(wi, s_w, &tot);
-    if (p < P) work[p] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) work[P] = carry;
-}
-
-// largest p in [lo, hi) with work[p] <= w
-__device__ __forceinline__ uint64_t item_pos(const uint64_t *work, uint64_t lo, uint64_t hi,
-                                             uint64_t w) {
-  while (hi - lo > 1) {
-    const uint64_t mid = (lo + hi) >> 1;
-    if (work[mid] <= w)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-template <bool kRows>
-__global__ __launch_bounds__(kSecThreads) void k_sec_draw(
-    const double *__restrict__ prob, const uint32_t *__restrict__ alias,
-    const TableRow *__restrict__ rows, uint64_t n, uint32_t log2r, uint64_t S,
-    const uint64_t *__restrict__ counts, const uint64_t *__restrict__ offsets,
-    const uint64_t *__restrict__ work, uint32_t k0, uint32_t k1, uint32_t table,
-    uint32_t *__restrict__ out) {
-  const uint64_t Sc = (S + 7) / 8;
-  const uint64_t cls = blockIdx.x % 8, nb = gridDim.x / 8;
-  const uint64_t p0 = cls * Sc, p1 = p0 + Sc;
-  const uint64_t wend = work[p1];
-  for (uint64_t w = work[p0] + blockIdx.x / 8; w < wend; w += nb) {
-    const uint64_t pp = item_pos(work, p0, p1, w);
-    const uint64_t s = sec_at(pp, Sc);
-    const uint64_t ws = work[pp];
-    const uint64_t c = counts[s];
-    const uint64_t j0 = (w - ws) * kSecItem;
-    const uint64_t j1 = (j0 + kSecItem < c) ? j0 + kSecItem : c;
-    const uint64_t base = s << log2r;
-    const uint64_t Rs = (n - base < (1ull << log2r)) ? n - base : (1ull << log2r);
-    const uint64_t o = offsets[s];
-    constexpr int U = kSecItem / kSecThreads;  // draws per thread
-    uint64_t row[U];
-    double coin[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t j = j0 + (uint64_t)u * kSecThreads + threadIdx.x;
-      u32x4 cc;
-      cc.x = (uint32_t)j;
-      cc.y = (uint32_t)(j >> 32);
-      cc.z = table;
-      cc.w = 2u + 4u * (uint32_t)s;
-      const u32x4 r = philox4x32_10(cc, k0, k1);
-      const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-      row[u] = base + __umul64hi(x, Rs);
-      const uint64_t uu = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
-      coin[u] = (double)uu * 0x1p-53;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint64_t j = j0 + (uint64_t)u * kSecThreads + threadIdx.x;
-      if (j < j1) {
-        uint32_t v;
-        if (kRows) {
-          const TableRow t = rows[row[u]];
-          v = (coin[u] < t.prob) ? (uint32_t)row[u] : t.alias;
-        } else {
-          v = (coin[u] < prob[row[u]]) ? (uint32_t)row[u] : alias[row[u]];
-        }
-        out[o + j] = v;
-      }
-    }
-  }
-}
-
-size_t sec_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r) {
-  SecLayout L;
-  if (!sec_layout(n, count, log2r, &L)) return 0;
-  return (size_t)L.total;
-}
-
-int launch_sample_sectioned(const double *prob, const uint32_t *alias, const TableRow *rows,
-                            uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
-                            uint32_t log2r, uint32_t *out, uint64_t *d_counts, void *d_ws,
-                            size_t ws_bytes, hipStream_t st) {
-  SecLayout L;
-  if (!sec_layout(n, count, log2r, &L)) return ALIAS_EINVAL;
-  if (ws_bytes < L.total) return ALIAS_EWORKSPACE;
-  char *ws = (char *)d_ws;
-  uint64_t *counts = d_counts ? d_counts : (uint64_t *)(ws + L.counts);
-  uint64_t *offsets = (uint64_t *)(ws + L.offsets), *work = (uint64_t *)(ws + L.work);
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  hipLaunchKernelGGL(k_sec_zero, dim3((uint32_t)((L.S + 255) / 256)), dim3(256), 0, st, counts,
-                     L.S);
-  uint64_t cb = ((count + 1) / 2 + kSecThreads * 16 - 1) / (kSecThreads * 16);
-  if (cb > 2048) cb = 2048;
-  if (cb == 0) cb = 1;
-  hipLaunchKernelGGL(k_sec_count, dim3((uint32_t)cb), dim3(kSecThreads), 0, st, n, count, log2r,
-                     L.S, k0, k1, table, (unsigned long long *)counts);
-  hipLaunchKernelGGL(k_sec_scan, dim3(1), dim3(1024), 0, st, counts, L.S, offsets, work);
-  // Few blocks (one per CU), each drawing kSecItem samples per work item:
-  // the fewer work items in flight, the fewer sections whose rows compete
-  // for an XCD's L2 (measured best on the 2^27-row table against 4x-16x
-  // more blocks or larger blocks).
-  uint64_t db = count / kSecItem + L.S;
-  if (db > 256) db = 256;
-  db = (db + 7) / 8 * 8;  // eight XCD classes of blocks
-  if (db == 0) db = 8;
-  if (rows)
-    hipLaunchKernelGGL(k_sec_draw<true>, dim3((uint32_t)db), dim3(kSecThreads), 0, st, nullptr,
-                       nullptr, rows, n, log2r, L.S, counts, offsets, work, k0, k1, table, out);
-  else
-    hipLaunchKernelGGL(k_sec_draw<false>, dim3((uint32_t)db), dim3(kSecThreads), 0, st, prob,
-                       alias, nullptr, n, log2r, L.S, counts, offsets, work, k0, k1, table, out);
-  return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
-}
-
 }  // namespace amdalias

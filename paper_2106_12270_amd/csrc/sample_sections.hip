@@ -1,7 +1,8 @@
-// Batched sectioned sampling: every table of a batch sampled section by
-// section (arXiv 2106.12270, Sec. 5, the sectioned methods), in one fixed
+// Sectioned sampling (arXiv 2106.12270, Sec. 5, the sectioned methods): one
+// table, or every table of a batch, sampled section by section in one fixed
 // sequence of launches with no host readback (so it can be captured into a
-// HIP graph together with the batched build).
+// HIP graph together with the batched build).  A single table is a batch of
+// one whose Philox table word is the caller's table id.
 //
 // Table t owns rows [offsets[t], offsets[t+1]) and output positions
 // [draw_off[t], draw_off[t+1]).  It gets exactly the draws that single-table
@@ -43,10 +44,20 @@
 
 namespace amdalias {
 
-constexpr int kBsThreads = 256;          // count and draw kernels
-constexpr int kBsPer = 16;               // output positions per thread per chunk
+#ifndef ALIAS_BS_PER
+#define ALIAS_BS_PER 16
+#endif
+#ifndef ALIAS_BS_DRAW_BLOCKS
+#define ALIAS_BS_DRAW_BLOCKS 1024
+#endif
+#ifndef ALIAS_BS_DRAW_BLOCKS_FEW
+#define ALIAS_BS_DRAW_BLOCKS_FEW 256
+#endif
+constexpr int kBsThreads = 256;             // count and draw kernels
+constexpr int kBsPer = ALIAS_BS_PER;        // output positions per thread per chunk
 constexpr uint64_t kBsChunk = (uint64_t)kBsThreads * kBsPer;
-constexpr uint32_t kBsHist = 4096;       // sections a count block histograms in LDS
+constexpr int kBsCountThreads = 1024;    // count kernel
+constexpr uint32_t kBsHistMax = 32768;   // sections a count block can histogram in LDS (128 KB)
 constexpr int kBsScanThreads = 1024;     // scan kernels
 constexpr int kBsScanPer = 4;            // consecutive items per scan thread
 constexpr uint64_t kBsScanBlock = (uint64_t)kBsScanThreads * kBsScanPer;
@@ -65,8 +76,8 @@ struct Two {
 };
 
 struct BsLayout {
-  uint64_t sec_start, pair_start, bsum, bpre, counts, sec_off, total;
-  uint64_t S_max, nb_max;
+  uint64_t sec_start, pair_start, bsum, bpre, counts, sec_off, sec_table, chunk_sec, total;
+  uint64_t S_max, nb_max, chunks;
 };
 
 inline bool bs_layout(uint32_t T, uint64_t total_items, uint64_t total_draws, uint32_t log2r,
@@ -92,6 +103,9 @@ inline bool bs_layout(uint32_t T, uint64_t total_items, uint64_t total_draws, ui
   L->bpre = take(L->nb_max * sizeof(Two));
   L->counts = take(L->S_max * 8);
   L->sec_off = take((L->S_max + 1) * 8);
+  L->chunks = (total_draws + kBsChunk - 1) / kBsChunk;
+  L->sec_table = take(L->S_max * 4);
+  L->chunk_sec = take((L->chunks + 1) * 4);
   L->total = off;
   return true;
 }
@@ -291,6 +305,14 @@ __global__ void k_bs_init(BsHeader *h) {
   }
 }
 
+__global__ void k_bs_copy_counts(const uint64_t *__restrict__ counts, const BsHeader *h,
+                                 uint64_t *__restrict__ out) {
+  const uint64_t S = h->sections;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = counts[i];
+}
+
 __global__ void k_bs_zero(uint64_t *counts, const BsHeader *h) {
   const uint64_t S = h->sections;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
@@ -314,36 +336,41 @@ __device__ __forceinline__ uint64_t find_le(const uint64_t *start, uint64_t lo, 
 // ---------------------------------------------------------------------------
 // Counts
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBsThreads) void k_bs_count(
+// One block of 1024 threads takes a contiguous range of virtual-draw pairs;
+// the sections that range can reach (those of its first to last table) are
+// counted in an LDS histogram of up to hist_cap entries (dynamic LDS), else
+// directly in global memory.
+__global__ __launch_bounds__(kBsCountThreads) void k_bs_count(
     const uint64_t *__restrict__ offsets, const uint64_t *__restrict__ draw_off, uint32_t T,
     uint64_t total_items, uint64_t total_draws, uint32_t log2r,
     const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ pair_start,
-    const BsHeader *h, uint32_t k0, uint32_t k1, unsigned long long *counts) {
-  __shared__ uint32_t hist[kBsHist];
+    const BsHeader *h, uint32_t k0, uint32_t k1, uint32_t table_base, uint32_t hist_cap,
+    unsigned long long *counts) {
+  extern __shared__ uint32_t hist[];
   if (h->flags & kBsBadOffsets) return;  // nothing is counted (uniform)
   // placeholder sections: all draws of a table without usable rows
-  for (uint64_t t = (uint64_t)blockIdx.x * kBsThreads + threadIdx.x; t < T;
-       t += (uint64_t)gridDim.x * kBsThreads) {
+  for (uint64_t t = (uint64_t)blockIdx.x * kBsCountThreads + threadIdx.x; t < T;
+       t += (uint64_t)gridDim.x * kBsCountThreads) {
     const BsTable q = bs_table(offsets, draw_off, t, total_items, total_draws);
     if (q.kind == 1 && q.c) atomicAdd(&counts[sec_start[t]], (unsigned long long)q.c);
   }
   const uint64_t P = h->pairs;
   uint64_t per = (P + gridDim.x - 1) / gridDim.x;
-  per = (per + kBsThreads - 1) / kBsThreads * kBsThreads;
+  per = (per + kBsCountThreads - 1) / kBsCountThreads * kBsCountThreads;
   const uint64_t g0 = (uint64_t)blockIdx.x * per;
   const uint64_t g1 = g0 + per < P ? g0 + per : P;
   if (g0 >= g1) return;  // uniform over the block
   const uint64_t tf = find_le(pair_start, 0, T, g0), tl = find_le(pair_start, tf, T, g1 - 1);
   const uint64_t sbase = sec_start[tf];
   const uint64_t span = sec_start[tl + 1] - sbase;
-  const bool lds = span <= kBsHist;
+  const bool lds = span <= hist_cap;
   if (lds)
-    for (uint64_t i = threadIdx.x; i < span; i += kBsThreads) hist[i] = 0;
+    for (uint64_t i = threadIdx.x; i < span; i += kBsCountThreads) hist[i] = 0;
   __syncthreads();
   uint64_t t = tf;
   uint64_t ps = pair_start[t], pe = pair_start[t + 1];
   uint64_t n = offsets[t + 1] - offsets[t], c = draw_off[t + 1] - draw_off[t], ss = sec_start[t];
-  for (uint64_t g = g0 + threadIdx.x; g < g1; g += kBsThreads) {
+  for (uint64_t g = g0 + threadIdx.x; g < g1; g += kBsCountThreads) {
     if (g >= pe) {
       // g < P = pair_start[T], so the table holding g is found before T
       t = find_le(pair_start, t + 1, tl + 1, g);
@@ -357,7 +384,7 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_count(
     u32x4 cc;
     cc.x = (uint32_t)b;
     cc.y = (uint32_t)(b >> 32);
-    cc.z = (uint32_t)t;
+    cc.z = table_base + (uint32_t)t;
     cc.w = 1u;
     const u32x4 r = philox4x32_10(cc, k0, k1);
     const uint64_t x0 = (uint64_t)r.x | ((uint64_t)r.y << 32);
@@ -375,9 +402,31 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_count(
   }
   if (lds) {
     __syncthreads();
-    for (uint64_t i = threadIdx.x; i < span; i += kBsThreads)
+    for (uint64_t i = threadIdx.x; i < span; i += kBsCountThreads)
       if (hist[i]) atomicAdd(&counts[sbase + i], (unsigned long long)hist[i]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Maps for the drawing kernel: the table of every section, and the section
+// of every chunk's first output position (both by binary search, one
+// thread per entry)
+// ---------------------------------------------------------------------------
+__global__ void k_bs_sec_table(const uint64_t *__restrict__ sec_start, uint32_t T,
+                               const BsHeader *h, uint32_t *__restrict__ sec_table) {
+  const uint64_t S = h->sections;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    sec_table[s] = (uint32_t)find_le(sec_start, 0, T, s);
+}
+
+__global__ void k_bs_chunk_map(const uint64_t *__restrict__ sec_off, const BsHeader *h,
+                               uint64_t chunks, uint32_t *__restrict__ chunk_sec) {
+  if (h->flags & kBsBadOffsets) return;  // the drawing kernel does not read the map
+  const uint64_t S = h->sections;
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < chunks;
+       c += (uint64_t)gridDim.x * blockDim.x)
+    chunk_sec[c] = (uint32_t)find_le(sec_off, 0, S, c * kBsChunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,7 +441,7 @@ struct BsSec {
 __device__ __forceinline__ BsSec bs_section(const uint64_t *__restrict__ offsets,
                                             const uint64_t *__restrict__ sec_start,
                                             const uint64_t *__restrict__ sec_off, uint64_t s,
-                                            uint64_t t, uint32_t log2r) {
+                                            uint64_t t, uint32_t log2r, uint32_t table_base) {
   BsSec q;
   const uint64_t a = offsets[t], n = offsets[t + 1] - a;
   const uint64_t ls = s - sec_start[t];
@@ -401,7 +450,7 @@ __device__ __forceinline__ BsSec bs_section(const uint64_t *__restrict__ offsets
   q.base = ls << log2r;
   q.Rs = q.ok ? (n - q.base < (1ull << log2r) ? n - q.base : (1ull << log2r)) : 0;
   q.so = sec_off[s];
-  q.t = (uint32_t)t;
+  q.t = table_base + (uint32_t)t;
   q.w = 2u + 4u * (uint32_t)ls;
   return q;
 }
@@ -441,7 +490,9 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
     const double *__restrict__ prob, const uint32_t *__restrict__ alias,
     const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t T,
     uint32_t log2r, const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
-    const BsHeader *h, uint64_t total_draws, uint32_t k0, uint32_t k1, uint32_t *__restrict__ out) {
+    const uint32_t *__restrict__ sec_table, const uint32_t *__restrict__ chunk_sec,
+    const BsHeader *h, uint64_t total_draws, uint32_t k0, uint32_t k1, uint32_t table_base,
+    uint32_t *__restrict__ out) {
   __shared__ BsSec s_q[kBsThreads];
   const uint64_t S = h->sections;
   const bool bad = (h->flags & kBsBadOffsets) != 0;
@@ -457,11 +508,15 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
       continue;
     }
     // consistent offsets: the sections' output ranges tile [0, total_draws)
-    const uint64_t sf = find_le(sec_off, 0, S, o0), sl = find_le(sec_off, sf, S, olast);
-    const uint64_t tf = find_le(sec_start, 0, T, sf);
+    // the sections of the chunk's first and last positions: the chunk map
+    // gives the first, and the next chunk's first bounds the last
+    const uint64_t sf = chunk_sec[ch];
+    const uint64_t sn = ch + 1 < C ? chunk_sec[ch + 1] : S - 1;
+    const uint64_t sl = find_le(sec_off, sf, sn + 1, olast);
+    const uint64_t tf = sec_table[sf];
     if (sf == sl) {
       // one section serves the whole chunk
-      const BsSec q = bs_section(offsets, sec_start, sec_off, sf, tf, log2r);
+      const BsSec q = bs_section(offsets, sec_start, sec_off, sf, tf, log2r, table_base);
       uint64_t row[kBsPer];
       double coin[kBsPer];
 #pragma unroll
@@ -477,15 +532,13 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
       }
       continue;
     }
-    const uint64_t tl = find_le(sec_start, tf, T, sl);
     const uint64_t m = sl - sf + 1;
     if (m <= kBsThreads) {
       // several sections, at most one per thread: their descriptions are
       // staged in LDS and each position finds its section there
       if (threadIdx.x < m) {
         const uint64_t s = sf + threadIdx.x;
-        s_q[threadIdx.x] = bs_section(offsets, sec_start, sec_off, s,
-                                      find_le(sec_start, tf, tl + 1, s), log2r);
+        s_q[threadIdx.x] = bs_section(offsets, sec_start, sec_off, s, sec_table[s], log2r, table_base);
       }
       __syncthreads();
 #pragma unroll 4
@@ -517,14 +570,30 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
       const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
       if (o > olast) break;
       s = find_le(sec_off, s, sl + 1, o);
-      t = find_le(sec_start, t, tl + 1, s);
-      const BsSec q = bs_section(offsets, sec_start, sec_off, s, t, log2r);
+      t = sec_table[s];
+      const BsSec q = bs_section(offsets, sec_start, sec_off, s, t, log2r, table_base);
       uint64_t row;
       double coin;
       bs_setup(q, o - q.so, k0, k1, row, coin);
       out[o] = q.ok ? bs_pick<kRows>(prob, alias, rows, q.a, row, coin) : 0xFFFFFFFFu;
     }
   }
+}
+
+// Largest dynamic LDS allocation of one block on the current device
+// (queried once per device).
+static size_t bs_max_lds() {
+  static size_t cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+      v = 65536;
+    cache[dev] = (size_t)v;
+  }
+  return cache[dev];
 }
 
 size_t bs_workspace_bytes(uint32_t T, uint64_t total_items, uint64_t total_draws,
@@ -539,6 +608,7 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
                                     const uint64_t *draw_off, uint32_t T, uint64_t total_items,
                                     uint64_t total_draws, uint64_t seed, uint32_t log2r,
                                     uint32_t *out, void *d_ws, size_t ws_bytes, int32_t *status,
+                                    uint32_t table_base, uint64_t *counts_out,
                                     uint32_t draw_blocks, hipStream_t st) {
   BsLayout L;
   if (!bs_layout(T, total_items, total_draws, log2r, &L)) return ALIAS_EINVAL;
@@ -548,6 +618,7 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   uint64_t *sec_start = (uint64_t *)(ws + L.sec_start), *pair_start = (uint64_t *)(ws + L.pair_start);
   Two *bsum = (Two *)(ws + L.bsum), *bpre = (Two *)(ws + L.bpre);
   uint64_t *counts = (uint64_t *)(ws + L.counts), *sec_off = (uint64_t *)(ws + L.sec_off);
+  uint32_t *sec_table = (uint32_t *)(ws + L.sec_table), *chunk_sec = (uint32_t *)(ws + L.chunk_sec);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 
   hipLaunchKernelGGL(k_bs_init, dim3(1), dim3(64), 0, st, h);
@@ -562,14 +633,24 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   uint64_t zb = (L.S_max + 255) / 256;
   if (zb > 4096) zb = 4096;
   hipLaunchKernelGGL(k_bs_zero, dim3((uint32_t)zb), dim3(256), 0, st, counts, (const BsHeader *)h);
-  // pairs <= total_draws / 2 + T; about 16 pairs per thread, at most 2048 blocks
-  uint64_t cb = (total_draws / 2 + T + kBsThreads * 16 - 1) / (kBsThreads * 16);
-  if (cb > 2048) cb = 2048;
+  hipLaunchKernelGGL(k_bs_sec_table, dim3((uint32_t)zb), dim3(256), 0, st,
+                     (const uint64_t *)sec_start, T, (const BsHeader *)h, sec_table);
+  // pairs <= total_draws / 2 + T; at least 32 pairs per thread, at most 512
+  // blocks (each zeroes and flushes its histogram once)
+  uint64_t cb = (total_draws / 2 + T + kBsCountThreads * 32 - 1) / (kBsCountThreads * 32);
+  if (cb > 512) cb = 512;
   if (cb == 0) cb = 1;
-  hipLaunchKernelGGL(k_bs_count, dim3((uint32_t)cb), dim3(kBsThreads), 0, st, offsets, draw_off, T,
-                     total_items, total_draws, log2r, (const uint64_t *)sec_start,
-                     (const uint64_t *)pair_start, (const BsHeader *)h, k0, k1,
+  uint64_t cap = L.S_max < kBsHistMax ? L.S_max : kBsHistMax;
+  const uint64_t lds_cap = bs_max_lds() / 4;
+  if (cap > lds_cap) cap = lds_cap;
+  hipLaunchKernelGGL(k_bs_count, dim3((uint32_t)cb), dim3(kBsCountThreads), (size_t)cap * 4, st,
+                     offsets, draw_off, T, total_items, total_draws, log2r,
+                     (const uint64_t *)sec_start, (const uint64_t *)pair_start,
+                     (const BsHeader *)h, k0, k1, table_base, (uint32_t)cap,
                      (unsigned long long *)counts);
+  if (counts_out)
+    hipLaunchKernelGGL(k_bs_copy_counts, dim3((uint32_t)zb), dim3(256), 0, st,
+                       (const uint64_t *)counts, (const BsHeader *)h, counts_out);
   const SectionSrc ss{(const uint64_t *)counts, h, sec_off};
   const uint32_t nbs = (uint32_t)((L.S_max + kBsScanBlock - 1) / kBsScanBlock);
   hipLaunchKernelGGL(k_bs_scan_reduce<SectionSrc>, dim3(nbs), dim3(kBsScanThreads), 0, st, ss,
@@ -578,20 +659,69 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
                      (const Two *)bsum, bpre, h, (int32_t *)nullptr);
   hipLaunchKernelGGL(k_bs_scan_down<SectionSrc>, dim3(nbs), dim3(kBsScanThreads), 0, st, ss,
                      (const Two *)bpre);
-  uint64_t db = draw_blocks ? draw_blocks : 256;
-  const uint64_t chunks = (total_draws + kBsChunk - 1) / kBsChunk;
+  uint64_t mb = (L.chunks + 255) / 256;
+  if (mb > 4096) mb = 4096;
+  if (mb == 0) mb = 1;
+  hipLaunchKernelGGL(k_bs_chunk_map, dim3((uint32_t)mb), dim3(256), 0, st,
+                     (const uint64_t *)sec_off, (const BsHeader *)h, L.chunks, chunk_sec);
+  // few blocks when sections hold many chunks (single large tables), more
+  // when most chunks span several sections (many small tables)
+  uint64_t db = draw_blocks;
+  if (db == 0) db = (total_draws / L.S_max >= 4 * kBsChunk) ? ALIAS_BS_DRAW_BLOCKS_FEW
+                                                           : ALIAS_BS_DRAW_BLOCKS;
+  const uint64_t chunks = L.chunks;
   if (db > chunks) db = chunks;
   db = (db + 7) / 8 * 8;  // eight block classes
   if (db == 0) db = 8;
   if (rows)
     hipLaunchKernelGGL(k_bs_draw<true>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, nullptr,
                        nullptr, rows, offsets, T, log2r, (const uint64_t *)sec_start,
-                       (const uint64_t *)sec_off, (const BsHeader *)h, total_draws, k0, k1, out);
+                       (const uint64_t *)sec_off, (const uint32_t *)sec_table,
+                       (const uint32_t *)chunk_sec, (const BsHeader *)h, total_draws, k0, k1,
+                       table_base, out);
   else
     hipLaunchKernelGGL(k_bs_draw<false>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, prob, alias,
                        nullptr, offsets, T, log2r, (const uint64_t *)sec_start,
-                       (const uint64_t *)sec_off, (const BsHeader *)h, total_draws, k0, k1, out);
+                       (const uint64_t *)sec_off, (const uint32_t *)sec_table,
+                       (const uint32_t *)chunk_sec, (const BsHeader *)h, total_draws, k0, k1,
+                       table_base, out);
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// One table: the batch machinery with T = 1 and the caller's table id.  The
+// workspace starts with the one-table offsets {0, n}, draw offsets
+// {0, count} and a status word, written on the device by the first launch.
+// ---------------------------------------------------------------------------
+__global__ void k_bs_single(uint64_t *head, uint64_t n, uint64_t count) {
+  if (threadIdx.x == 0) {
+    head[0] = 0;
+    head[1] = n;
+    head[2] = 0;
+    head[3] = count;
+    head[4] = 0;
+  }
+}
+
+size_t sec_workspace_bytes(uint64_t n, uint64_t count, uint32_t log2r) {
+  if (n == 0 || n > 0xFFFFFFFFull || log2r < 6 || log2r > 31 || count > (1ull << 40)) return 0;
+  if (((n + (1ull << log2r) - 1) >> log2r) > (1ull << 20)) return 0;
+  const size_t b = bs_workspace_bytes(1, n, count, log2r);
+  return b ? 256 + b : 0;
+}
+
+int launch_sample_sectioned(const double *prob, const uint32_t *alias, const TableRow *rows,
+                            uint64_t n, uint64_t count, uint64_t seed, uint32_t table,
+                            uint32_t log2r, uint32_t *out, uint64_t *d_counts, void *d_ws,
+                            size_t ws_bytes, hipStream_t st) {
+  const size_t need = sec_workspace_bytes(n, count, log2r);
+  if (need == 0) return ALIAS_EINVAL;
+  if (ws_bytes < need) return ALIAS_EWORKSPACE;
+  uint64_t *head = (uint64_t *)d_ws;
+  hipLaunchKernelGGL(k_bs_single, dim3(1), dim3(64), 0, st, head, n, count);
+  return launch_sample_batched_sectioned(prob, alias, rows, head, head + 2, 1, n, count, seed, log2r,
+                                         out, (char *)d_ws + 256, ws_bytes - 256,
+                                         (int32_t *)(head + 4), table, d_counts, 0, st);
 }
 
 }  // namespace amdalias
