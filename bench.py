@@ -43,6 +43,8 @@ def parse():
                     help="skip the learned-vs-binary split comparison")
     ap.add_argument("--no-sectioned", action="store_true",
                     help="skip the sectioned-sampling measurement")
+    ap.add_argument("--sectioned-log2r", default="13,14,16",
+                    help="section sizes (log2 rows) of the sectioned-sampling measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched-table workloads (profiling)")
     ap.add_argument("--no-loop", action="store_true",
@@ -474,7 +476,7 @@ def main():
     # same table: the 10^9 draws again, timed on the same stream
     if rows_layout and not args.no_sectioned:
         sec = {}
-        for log2r in (13, 14, 16):
+        for log2r in [int(x) for x in args.sectioned_log2r.split(",")]:
             ss = pkg.SectionedSampler(n, draws, log2r, device=dev)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
             ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, out=out, stream=stream)

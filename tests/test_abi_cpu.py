@@ -182,6 +182,40 @@ def test_batched_entry_points_reject_bad_arguments_before_launching():
     assert sr(fake, fake, T, total, fake, 100, 1, None, fake, None) == pkg.ALIAS_EINVAL
 
 
+def test_sectioned_workspace_and_argument_rules():
+    """Sectioned sampling (one table and batched): workspace sizes and the
+    argument checks made before any launch."""
+    L = pkg.lib()
+    one = L.alias_sample_sectioned_workspace_bytes(100_000, 10**6, 12)
+    bat = L.alias_sample_batched_sectioned_workspace_bytes(1, 100_000, 10**6, 12)
+    assert bat > 0 and one == bat + 256  # one table: the batch of one plus its offsets
+    many = L.alias_sample_batched_sectioned_workspace_bytes(100_000, 788_000_000, 1 << 30, 12)
+    assert 0 < many < (1 << 26)  # per-section and per-table arrays only
+    assert L.alias_sample_batched_sectioned_workspace_bytes((1 << 20) + 1, 1 << 22, 10, 12) == 0
+    assert L.alias_sample_batched_sectioned_workspace_bytes(4, 1 << 40, 10, 6) == 0  # > 2^32 sections
+    assert L.alias_sample_sectioned_workspace_bytes(1 << 27, 10, 6) == 0  # > 2^20 sections
+    fake = C.c_void_p(0x10000)
+    f4 = C.c_void_p(0x10004)
+    T, total, nd, lg = 3, 1000, 5000, 8
+    wsb = L.alias_sample_batched_sectioned_workspace_bytes(T, total, nd, lg)
+    sr = L.alias_sample_batched_sectioned_rows
+    assert sr(fake, fake, T, total, fake, nd, 1, lg, fake, fake, wsb - 1, fake,
+              None) == pkg.ALIAS_EWORKSPACE
+    assert sr(f4, fake, T, total, fake, nd, 1, lg, fake, fake, wsb, fake, None) == pkg.ALIAS_EINVAL
+    assert sr(fake, None, T, total, fake, nd, 1, lg, fake, fake, wsb, fake, None) == pkg.ALIAS_EINVAL
+    assert sr(fake, fake, T, total, fake, nd, 1, lg, None, fake, wsb, fake, None) == pkg.ALIAS_EINVAL
+    assert sr(fake, fake, T, total, fake, nd, 1, lg, fake, f4, wsb, fake, None) == pkg.ALIAS_EINVAL
+    assert sr(fake, fake, T, total, fake, nd, 1, 5, fake, fake, wsb, fake, None) == pkg.ALIAS_EINVAL
+    sb = L.alias_sample_batched_sectioned
+    assert sb(None, fake, fake, T, total, fake, nd, 1, lg, fake, fake, wsb, fake,
+              None) == pkg.ALIAS_EINVAL
+    assert sb(fake, fake, fake, T, total, fake, nd, 1, lg, fake, fake, wsb, None,
+              None) == pkg.ALIAS_EINVAL
+    ws1 = L.alias_sample_sectioned_workspace_bytes(total, nd, lg)
+    assert L.alias_sample_sectioned_rows(fake, total, nd, 1, 0, lg, fake, None, fake, ws1 - 1,
+                                         None) == pkg.ALIAS_EWORKSPACE
+
+
 def test_product_package_does_not_use_the_oracle():
     pkg_dir = os.path.join(ROOT, "paper_2106_12270_amd")
     for dirpath, _, files in os.walk(pkg_dir):
