@@ -62,6 +62,25 @@ def batched_build(w, off, chunk=None, rows=False, **kw):
     return bb, bb.status.cpu().numpy(), p.cpu().numpy(), a.cpu().numpy().view(np.uint32)
 
 
+def oracle_tables(w, off, chunk=1024):
+    """Every table of the batch built by the oracle (empty tables skipped)."""
+    p = np.zeros(len(w))
+    a = np.zeros(len(w), np.uint32)
+    for t in range(len(off) - 1):
+        s, e = int(off[t]), int(off[t + 1])
+        if e > s:
+            p[s:e], a[s:e] = oracle.psa_build(w[s:e], chunk=chunk)
+    return p, a
+
+
+def to_rows(p, a):
+    """A table as 16-byte device rows {prob, alias, 0}."""
+    r = torch.zeros((len(p), 4), dtype=torch.int32, device=DEV)
+    r.view(torch.float64)[:, 0] = torch.from_numpy(p).to(DEV)
+    r[:, 2] = torch.from_numpy(a.view(np.int32)).to(DEV)
+    return r
+
+
 def ulp_diff(a, b):
     return np.abs(a.view(np.int64) - b.view(np.int64))
 
@@ -161,13 +180,11 @@ def test_batched_samples_bit_exact(rows):
     doff = inputs.offsets_from_sizes(draws)
     total = int(doff[-1])
     say("batched samples", rows)
-    res = batched_build(w, off, 256, rows=rows)
-    st, p, a = res[1], res[2], res[3]
-    assert (st == 0).all()
+    p, a = oracle_tables(w, off, 256)  # the oracle's tables, sampled on both sides
     out = torch.full((total,), -7, dtype=torch.int32, device=DEV)
     seed = inputs.SAMPLE_SEED + 3
     if rows:
-        out, sst = pkg.sample_batched_rows(res[4], dev_u64(off), dev_u64(doff), seed, out)
+        out, sst = pkg.sample_batched_rows(to_rows(p, a), dev_u64(off), dev_u64(doff), seed, out)
     else:
         out, sst = pkg.sample_batched(torch.from_numpy(p).to(DEV),
                                       torch.from_numpy(a.view(np.int32)).to(DEV), dev_u64(off),
@@ -186,8 +203,7 @@ def test_batched_sampler_rejects_bad_offsets():
     sizes = [10, 0, 20]
     w = inputs.uniform01(30, 2)
     off = inputs.offsets_from_sizes(sizes)
-    res = batched_build(w, off, 64)
-    p, a = res[2], res[3]
+    p, a = oracle_tables(w, off, 64)
     draws = np.array([5, 3, 4])  # table 1 is empty but gets draws
     doff = inputs.offsets_from_sizes(draws)
     out = torch.zeros(12, dtype=torch.int32, device=DEV)
@@ -286,7 +302,8 @@ def test_learned_split_per_table_models():
 @pytest.mark.parametrize("name", ["batch_100k_16_65536", "batch_1024_2p14_2p22"])
 def test_full_size_batches_sampled_tables(name):
     """The batched workloads at full size: sampled tables against the oracle
-    (invariant, aliases, 2 ulp) and their draws bit-exact."""
+    (invariant, aliases, 2 ulp); then those tables are replaced by the
+    oracle's and the batched draws of each are bit-exact with the oracle's."""
     say("full batch", name, "generating")
     w, off, doff = inputs.make_batch(name)
     T, total, nd = len(off) - 1, len(w), int(doff[-1])
@@ -296,18 +313,14 @@ def test_full_size_batches_sampled_tables(name):
     od, dd_ = dev_u64(off), dev_u64(doff)
     rows = bb.build_rows(wd, od)
     del wd
-    out = torch.empty(nd, dtype=torch.int32, device=DEV)
-    seed = inputs.SAMPLE_SEED
-    out, sst = pkg.sample_batched_rows(rows, od, dd_, seed, out)
     torch.cuda.synchronize()
     assert (bb.status == 0).all()
-    assert int(sst.item()) == 0
     rng = np.random.default_rng(1)
     picks = sorted(set(rng.integers(0, T, size=6).tolist()) | {0, T - 1,
                    int(np.argmax(np.diff(off.astype(np.int64))))})
+    tabs = {}
     for t in picks:
         s, e = int(off[t]), int(off[t + 1])
-        ds, de = int(doff[t]), int(doff[t + 1])
         pr, al = pkg.rows_split(rows[s:e])
         p = pr.cpu().numpy()
         a = al.cpu().numpy().view(np.uint32)
@@ -316,8 +329,18 @@ def test_full_size_batches_sampled_tables(name):
         assert ulp_diff(p, op).max() <= 2, t
         r = oracle.check(w[s:e], p, a)
         assert r["max_rel"] <= 1e-12 and r["zero_violations"] == 0, (t, r)
+        tabs[t] = (op, oa)
+        rows[s:e] = to_rows(op, oa)  # the sampled tables are the oracle's
+    out = torch.empty(nd, dtype=torch.int32, device=DEV)
+    seed = inputs.SAMPLE_SEED
+    out, sst = pkg.sample_batched_rows(rows, od, dd_, seed, out)
+    torch.cuda.synchronize()
+    assert int(sst.item()) == 0
+    for t in picks:
+        ds, de = int(doff[t]), int(doff[t + 1])
+        op, oa = tabs[t]
         k = min(de - ds, 200_000)
-        ref = oracle.sample(p, a, k, seed, first=0, table=t)
+        ref = oracle.sample(op, oa, k, seed, first=0, table=t)
         assert np.array_equal(out[ds:ds + k].cpu().numpy().view(np.uint32), ref), t
 
 

@@ -50,6 +50,14 @@ def gpu_build(w, chunk=None, split="binary", model=None):
     return b, st, prob.cpu().numpy(), alias.cpu().numpy().view(np.uint32)
 
 
+def to_rows(p, a):
+    """A table as 16-byte device rows {prob, alias, 0}."""
+    r = torch.zeros((len(p), 4), dtype=torch.int32, device=DEV)
+    r.view(torch.float64)[:, 0] = torch.from_numpy(p).to(DEV)
+    r[:, 2] = torch.from_numpy(a.view(np.int32)).to(DEV)
+    return r
+
+
 def ulp_diff(a, b):
     ai = a.view(np.int64)
     bi = b.view(np.int64)
@@ -146,15 +154,22 @@ def test_row_layout_equals_two_array_layout(name, n):
     assert np.array_equal(r[:, :2].copy().view(np.float64).ravel(), p)
     assert np.array_equal(r[:, 2].view(np.uint32), a)
     assert np.all(r[:, 3] == 0)
-    # same draws from both layouts, and equal to the oracle's
+    # the same draws from both layouts of the GPU table
     pd = torch.from_numpy(p).to(DEV)
     ad = torch.from_numpy(a.view(np.int32)).to(DEV)
     o1 = pkg.sample(pd, ad, 300_001, 77, first_draw=12345)
     o2 = pkg.sample_rows(rows, 300_001, 77, first_draw=12345)
     torch.cuda.synchronize()
-    ref = oracle.sample(p, a, 300_001, 77, first=12345)
-    assert np.array_equal(o1.cpu().numpy().view(np.uint32), ref)
-    assert np.array_equal(o2.cpu().numpy().view(np.uint32), ref)
+    assert torch.equal(o1, o2)
+    # both layouts of the oracle's table: draws equal to the oracle's
+    op, oa = oracle.psa_build(w, chunk=1024)
+    o3 = pkg.sample(torch.from_numpy(op).to(DEV), torch.from_numpy(oa.view(np.int32)).to(DEV),
+                    300_001, 77, first_draw=12345)
+    o4 = pkg.sample_rows(to_rows(op, oa), 300_001, 77, first_draw=12345)
+    torch.cuda.synchronize()
+    ref = oracle.sample(op, oa, 300_001, 77, first=12345)
+    assert np.array_equal(o3.cpu().numpy().view(np.uint32), ref)
+    assert np.array_equal(o4.cpu().numpy().view(np.uint32), ref)
 
 
 def test_build_is_deterministic():
@@ -201,10 +216,10 @@ def test_invalid_weights_reported_on_device(bad):
 # --------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def table_2p20():
+    """The oracle's table of the 2^20 uniform workload (sampled on both sides)."""
     w = inputs.make_weights("uniform_2p20")
     say("table uniform_2p20")
-    _, st, p, a = gpu_build(w)
-    assert st == 0
+    p, a = oracle.psa_build(w, chunk=1024)
     return w, p, a
 
 
@@ -257,13 +272,13 @@ def test_fullsize_powerlaw_2p27():
     say("fullsize powerlaw_2p27 oracle check")
     r = oracle.check(w, p, a)
     assert r["max_rel"] <= 1e-12 and r["zero_violations"] == 0, r
-    # sampled draws across the 10^9-draw range, bit-exact
+    # sampled draws across the 10^9-draw range from the oracle's table, bit-exact
     say("fullsize powerlaw_2p27 sampled draws")
-    pd = torch.from_numpy(p).to(DEV)
-    ad = torch.from_numpy(a.view(np.int32)).to(DEV)
+    op, oa = oracle.psa_build(w, chunk=cfg["chunk"])
+    rows = to_rows(op, oa)
     for first in (0, 123_456_789, 10**9 - 100_000):
-        out = pkg.sample(pd, ad, 100_000, inputs.SAMPLE_SEED, first_draw=first)
-        ref = oracle.sample(p, a, 100_000, inputs.SAMPLE_SEED, first=first)
+        out = pkg.sample_rows(rows, 100_000, inputs.SAMPLE_SEED, first_draw=first)
+        ref = oracle.sample(op, oa, 100_000, inputs.SAMPLE_SEED, first=first)
         assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
 
 

@@ -78,20 +78,18 @@ def test_sectioned_full_size_windows():
     n, count, log2r = cfg["n"], cfg["draws"], 16
     say("sectioned full", n, count)
     w = inputs.make_weights(name)
-    b = pkg.Builder(n, cfg["chunk"], device=DEV)
-    rows = b.build_rows(torch.from_numpy(w).to(DEV))
+    p, a = oracle.psa_build(w, chunk=cfg["chunk"])  # the oracle's table, sampled on both sides
+    rows = torch.zeros((n, 4), dtype=torch.int32, device=DEV)
+    rows.view(torch.float64)[:, 0] = torch.from_numpy(p).to(DEV)
+    rows[:, 2] = torch.from_numpy(a.view(np.int32)).to(DEV)
     ss = pkg.SectionedSampler(n, count, log2r, device=DEV)
     counts = torch.zeros(ss.sections, dtype=torch.int64, device=DEV)
     out = ss.sample_rows(rows, inputs.SAMPLE_SEED, 0, counts=counts)
     torch.cuda.synchronize()
-    assert int(b.status.item()) == 0
     c = counts.cpu().numpy().view(np.uint64)
     assert int(c.sum()) == count
     # every section count against the oracle's
     assert np.array_equal(c, oracle.sectioned_counts(n, count, inputs.SAMPLE_SEED, log2r))
-    prob, alias = pkg.rows_split(rows)
-    p = prob.cpu().numpy()
-    a = alias.cpu().numpy().view(np.uint32)
     off = np.concatenate([[0], np.cumsum(c)]).astype(np.int64)
     rng = np.random.default_rng(3)
     for s in sorted(set(rng.integers(0, len(c), 4).tolist()) | {0, len(c) - 1}):
