@@ -123,7 +123,8 @@ def cpu_baseline(name, cpu_n, draws_sample):
 def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
     """Learned vs binary split on the 2^28 lognormal(0, 2) workload and its
     sorted-descending variant: split-kernel time on the same partition
-    (alias_resplit), full build time, model fit time, fallbacks."""
+    (alias_resplit; also the partial p-ary search), full build time, model
+    fit time, fallbacks."""
     import torch
 
     name = "lognormal_2p28"
@@ -160,6 +161,7 @@ def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
         fit_ms = ev[0].elapsed_time(ev[1])
         _, _, eps, _ = pkg.model_header(model)
         t_bin = timed(lambda: b.resplit(None), reps)
+        t_pary = timed(lambda: b.resplit(None, method="pary"), reps)
         t_lrn = timed(lambda: b.resplit(model), reps)
         fallbacks = int(b.header().split_fallbacks)
         bl = pkg.Builder(n, chunk, "learned", model, device=dev)
@@ -169,6 +171,7 @@ def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
             "fit_ms": round(fit_ms, 3), "final_loss": float(loss.item()), "eps": eps,
             "split_ms_binary": round(t_bin, 4), "split_ms_learned": round(t_lrn, 4),
             "split_speedup": round(t_bin / t_lrn, 3), "fallbacks": fallbacks,
+            "split_ms_pary": round(t_pary, 4), "split_speedup_pary": round(t_bin / t_pary, 3),
             "build_ms_binary": round(t_build_bin, 4), "build_ms_learned": round(t_build_lrn, 4),
             "build_speedup": round(t_build_bin / t_build_lrn, 4),
             "fit_amortised_after_builds": (round(fit_ms / (t_build_bin - t_build_lrn), 1)

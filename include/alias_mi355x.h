@@ -53,8 +53,12 @@ enum {
 /* Split methods (how each section's starting state is found, Sec. 4.1). */
 enum {
   ALIAS_SPLIT_BINARY = 0, /* binary search on the light/heavy prefix sums */
-  ALIAS_SPLIT_LEARNED = 1 /* model prediction + bracket check + search in the
-                             bracket; full binary search when the bracket fails */
+  ALIAS_SPLIT_LEARNED = 1, /* model prediction + bracket check + search in the
+                              bracket; full binary search when the bracket fails */
+  ALIAS_SPLIT_PARY = 2    /* partial p-ary search (Sec. 4.1, Alg. 1): the 64
+                             boundaries of a wave first narrow one shared range
+                             with 64 pivots per round, then each finishes by
+                             binary search inside it.  Same splits as binary. */
 };
 
 /* Build options; a zero-initialised struct selects the defaults. */
@@ -435,7 +439,7 @@ int alias_split_model_fit_batched(const void *d_build_ws, const uint64_t *d_offs
                                   double *d_loss, void *stream);
 
 /* Recompute the splits of a finished build in d_ws with the split method in
- * opts (binary, or learned with a model); the partition and prefix sums are
+ * opts (binary, partial p-ary, or learned with a model); the partition and prefix sums are
  * reused and the table is not rewritten.  The number of sections whose
  * bracket check failed is left in the workspace header (split_fallbacks). */
 int alias_resplit(void *d_ws, uint64_t n, const alias_build_opts *opts, void *stream);

@@ -13,7 +13,7 @@ __all__ = [
     "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
     "sample", "build_rows", "sample_rows", "rows_split", "Builder", "status_str",
     "BatchBuilder", "sample_batched", "sample_batched_rows", "SectionedSampler",
-    "SPLIT_BINARY", "SPLIT_LEARNED", "ALIAS_OK",
+    "SPLIT_BINARY", "SPLIT_LEARNED", "SPLIT_PARY", "ALIAS_OK",
     "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
 ]
 
@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libalias_mi355x.so")
 ALIAS_OK, ALIAS_EINVAL, ALIAS_EWEIGHTS, ALIAS_EWORKSPACE, ALIAS_EHIP, ALIAS_EMODEL = (
     0, -1, -2, -3, -4, -5)
 ALIAS_EINTERNAL = -6
-SPLIT_BINARY, SPLIT_LEARNED = 0, 1
+SPLIT_BINARY, SPLIT_LEARNED, SPLIT_PARY = 0, 1, 2
 MODEL_PWL, MODEL_MLP = 1, 2
 MODEL_KINDS = {"pwl": MODEL_PWL, "mlp": MODEL_MLP}
 
@@ -157,6 +157,8 @@ def _opts(chunk=None, split="binary", model=None, model_stride=0, pack_waves=0):
     o.chunk_items = 0 if chunk is None else int(chunk)
     if split in ("binary", SPLIT_BINARY):
         o.split_method = SPLIT_BINARY
+    elif split in ("pary", SPLIT_PARY):
+        o.split_method = SPLIT_PARY
     elif split in ("learned", SPLIT_LEARNED):
         o.split_method = SPLIT_LEARNED
         if model is not None:
@@ -285,10 +287,10 @@ class Builder:
         self._train_ws = tws
         return model, loss
 
-    def resplit(self, model=None, stream=None):
-        """Recompute the splits of the last build: binary if model is None,
-        else learned with that model."""
-        o = _opts(self.chunk, "learned" if model is not None else "binary", model)
+    def resplit(self, model=None, stream=None, method="binary"):
+        """Recompute the splits of the last build: learned with `model` if one
+        is given, else by `method` ("binary" or "pary")."""
+        o = _opts(self.chunk, "learned" if model is not None else method, model)
         st = lib().alias_resplit(C.c_void_p(self.ws.data_ptr()), self.n, C.byref(o),
                                  _stream(stream))
         if st:

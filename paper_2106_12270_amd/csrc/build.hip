@@ -58,6 +58,7 @@ struct Batch {
   int32_t *status;           // T status words
   const unsigned char *models;  // learned split: model blobs (or nullptr)
   uint64_t model_bytes, model_stride;
+  uint32_t split_pary;          // partial p-ary split search
   uint64_t tiles_max, secs_max, groups_max;
 };
 
@@ -805,18 +806,76 @@ __device__ __forceinline__ uint64_t split_fine(const SplitCtx &c, int64_t qstar,
   return j;
 }
 
+// The predicate of one boundary extended to every q: the answer lies in
+// [qa - 1, qb], so below qa it holds and above qb it fails.
+__device__ __forceinline__ bool pred_ext(const SplitCtx &c, int64_t q, uint64_t qa, int64_t qb) {
+  if (q < (int64_t)qa) return true;
+  if (q > qb) return false;
+  return pred_q(c, (uint64_t)q);
+}
+
+__device__ __forceinline__ dd shfl_dd(dd v, int src) {
+  return dd_make(__shfl(v.hi, src, 64), __shfl(v.lo, src, 64));
+}
+
+// Partial p-ary search (Sec. 4.1, Alg. 1) over the coarse range of a wave's
+// 64 consecutive boundaries of one table.  Their answers do not decrease
+// with m, so a pivot at which the first boundary's predicate holds lies at
+// or below every answer, and one at which the last boundary's fails lies
+// above every answer.  Each round the 64 lanes test 64 pivots spread over
+// the shared range [A, Z] and keep the part between the last "below" and
+// the first "above" pivot; rounds stop when the range no longer shrinks by
+// 4x.  Each lane then checks the ends of the shared range against its own
+// predicate (a failed check keeps its full range) before its binary search.
+__device__ __forceinline__ void pary_narrow(const SplitCtx &c, uint64_t qa, int64_t qb,
+                                            int64_t *lo, int64_t *hi) {
+  const int lane = threadIdx.x & 63;
+  SplitCtx c0 = c, c1 = c;
+  c0.m = __shfl(c.m, 0, 64);
+  c0.mavg = shfl_dd(c.mavg, 0);
+  c1.m = __shfl(c.m, 63, 64);
+  c1.mavg = shfl_dd(c.mavg, 63);
+  const uint64_t qa0 = __shfl(qa, 0, 64), qa1 = __shfl(qa, 63, 64);
+  const int64_t qb0 = __shfl(qb, 0, 64), qb1 = __shfl(qb, 63, 64);
+  int64_t A = __shfl(*lo, 0, 64), Z = __shfl(*hi, 63, 64);
+  for (int round = 0; round < 4 && Z - A > 64; ++round) {
+    const int64_t w = Z - A;
+    const int64_t s = A + (w * lane) / 63;
+    const uint64_t below = __ballot(pred_ext(c0, s, qa0, qb0));   // a prefix of lanes
+    const uint64_t above = __ballot(!pred_ext(c1, s, qa1, qb1));  // a suffix of lanes
+    const int nA = below ? 63 - __clzll((long long)below) : -1;
+    const int nZ = above ? __ffsll((long long)above) - 1 : 64;
+    const int64_t A2 = nA >= 0 ? A + (w * nA) / 63 : A;
+    const int64_t Z2 = nZ < 64 ? A + (w * nZ) / 63 - 1 : Z;
+    const bool enough = (Z2 - A2) * 4 <= w;
+    A = A2;
+    Z = Z2;
+    if (!enough) break;
+  }
+  // this lane's bracket [a, b] inside its own range, checked
+  const int64_t a = A > *lo ? A : *lo, b = Z < *hi ? Z : *hi;
+  bool ok = a <= b;
+  if (ok && a > *lo) ok = pred_ext(c, a, qa, qb);
+  if (ok && b < *hi) ok = !pred_ext(c, b + 1, qa, qb);
+  if (ok) {
+    *lo = a;
+    *hi = b;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_split(Batch B) {
   if (B.flags[0]) return;
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B.sec_start[B.T] + B.T) return;
-  const uint32_t t = find_table_bnd(B.sec_start, B.T, b);
+  // no lane leaves before the wave's partial p-ary phase
+  bool active = b < B.sec_start[B.T] + B.T;
+  const uint32_t t = active ? find_table_bnd(B.sec_start, B.T, b) : 0u;
   const alias_ws_header &h = B.hdr[t];
-  if (h.status != ALIAS_OK) return;
+  if (h.status != ALIAS_OK) active = false;
   const uint64_t k = b - (B.sec_start[t] + t);  // table-local boundary
   uint64_t off, n;
   table_range(B, t, off, n);
   const SplitModel *model = nullptr;
-  if (B.models) {
+  if (active && B.models) {
     model = (const SplitModel *)(B.models + (uint64_t)t * B.model_stride);
     if (!model_usable(model, B.model_bytes)) {
       // an unusable model is never read past its header; the split falls back
@@ -835,18 +894,25 @@ __global__ __launch_bounds__(256) void k_split(Batch B) {
   c.m = (k * B.chunk < n) ? k * B.chunk : n;
   const dd avg = dd_make(h.avg_hi, h.avg_lo);
   c.sl_tot = dd_make(h.sl_hi, h.sl_lo);
-  if (c.m == n) {
+  const bool last = active && c.m == n;
+  if (last) {
     B.split_i[b] = (uint32_t)c.L;
     B.split_j[b] = (uint32_t)c.H;
     B.spill[b] = dd_make(0.0, 0.0);
-    return;
   }
+  const bool search = active && !last;
   c.mavg = mul_d(avg, (double)c.m);
   const uint64_t jlo = c.m > c.L ? c.m - c.L : 0;
   const uint64_t jhi = c.m < c.H ? c.m : c.H;
   const uint64_t qa = (jlo + kAggStride - 1) / kAggStride;
   const int64_t qb = (int64_t)(jhi / kAggStride);
   int64_t lo = (int64_t)qa - 1, hi = qb;  // answer in [qa-1, qb]
+  if (B.split_pary) {
+    // every lane searching, all in one table (uniform over the wave)
+    const uint32_t t0 = __shfl(t, 0, 64);
+    if (__ballot(search && t == t0) == ~0ull) pary_narrow(c, qa, qb, &lo, &hi);
+  }
+  if (!search) return;
   if (model) {
     // learned: bracket [p - eps, p + eps] around the model's prediction
     const int64_t p = learned_predict_q(model, c.m, n, c.H);
@@ -1230,6 +1296,7 @@ static Batch make_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n
   B.spill = (dd *)(ws + Lo.pub.spill);
   B.status = d_status;
   B.models = models;
+  B.split_pary = Lo.split_method == ALIAS_SPLIT_PARY ? 1u : 0u;
   B.model_bytes = model_bytes;
   B.model_stride = model_stride;
   B.tiles_max = Lo.tiles_max;

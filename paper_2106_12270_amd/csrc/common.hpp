@@ -64,7 +64,7 @@ struct Layout {
   uint64_t sscr;        // setup scratch: uint64[3 * setup blocks]
   uint64_t flags;       // uint32[16]: [0] = inconsistent batch description
   uint64_t tiles_max, secs_max, groups_max, total;
-  uint32_t T, chunk, pack_waves;
+  uint32_t T, chunk, pack_waves, split_method;
 };
 
 constexpr uint32_t kMaxTables = 1u << 20;
@@ -87,10 +87,11 @@ inline uint32_t pack_waves_for(uint32_t chunk, uint32_t requested) {
 // Computes the workspace layout; returns false for invalid arguments.
 inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_opts *o, Layout *L) {
   if (T == 0 || T > kMaxTables || total == 0 || total > (1ull << 40)) return false;
-  uint32_t chunk = kDefaultChunk, waves = 0;
+  uint32_t chunk = kDefaultChunk, waves = 0, split = ALIAS_SPLIT_BINARY;
   if (o) {
     if (o->chunk_items) chunk = o->chunk_items;
-    if (o->split_method > ALIAS_SPLIT_LEARNED) return false;
+    if (o->split_method > ALIAS_SPLIT_PARY) return false;
+    split = o->split_method;
     waves = o->pack_waves;
     if (o->reserved) return false;
   }
@@ -141,6 +142,7 @@ inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_o
   L->T = T;
   L->chunk = chunk;
   L->pack_waves = waves;
+  L->split_method = split;
   return true;
 }
 
