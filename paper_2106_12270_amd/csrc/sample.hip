@@ -172,14 +172,25 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_batched(
     const double *__restrict__ prob, const uint32_t *__restrict__ alias,
     const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets,
     const uint64_t *__restrict__ draw_off, uint32_t T, uint64_t total_items, uint64_t total_draws,
-    uint32_t k0, uint32_t k1, uint32_t *__restrict__ out, int32_t *status) {
+    uint32_t k0, uint32_t k1, uint32_t xcd_classes, uint32_t *__restrict__ out,
+    int32_t *status) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const bool ok = draw_off[0] == 0 && draw_off[T] == total_draws && offsets[0] == 0 &&
                     offsets[T] == total_items;
     if (!ok) *status = ALIAS_EINVAL;
   }
-  for (uint64_t c0 = (uint64_t)blockIdx.x * kBatchChunk; c0 < total_draws;
-       c0 += (uint64_t)gridDim.x * kBatchChunk) {
+  // With small tables the chunks are dealt to eight block classes (block
+  // b % 8 runs on one XCD under round-robin dispatch): class c takes the
+  // c-th eighth of the draws in order, so a table's draws are served by one
+  // XCD and its rows are fetched into one L2 instead of several.  Large
+  // tables (gathers from HBM either way) keep the plain grid stride.
+  const uint64_t C = (total_draws + kBatchChunk - 1) / kBatchChunk;
+  const uint64_t ncls = xcd_classes ? 8 : 1;
+  const uint64_t Rg = (C + ncls - 1) / ncls;
+  const uint64_t cls = blockIdx.x % ncls, nb = gridDim.x / ncls;
+  const uint64_t cend = (cls + 1) * Rg < C ? (cls + 1) * Rg : C;
+  for (uint64_t ch = cls * Rg + blockIdx.x / ncls; ch < cend; ch += nb) {
+    const uint64_t c0 = ch * kBatchChunk;
     const uint64_t clast = (c0 + kBatchChunk < total_draws ? c0 + kBatchChunk : total_draws) - 1;
     // the chunk's first and last tables (the same for every thread of the block)
     const uint32_t tf = find_first_le(draw_off, T, c0);
@@ -242,16 +253,19 @@ int launch_sample_batched(const double *prob, const uint32_t *alias, const Table
                           uint32_t *out, int32_t *status, hipStream_t st) {
   uint64_t blocks = (total_draws + kBatchChunk - 1) / kBatchChunk;
   if (blocks > 16384) blocks = 16384;
-  if (blocks == 0) blocks = 1;
+  blocks = (blocks + 7) / 8 * 8;  // a multiple of the eight block classes
+  if (blocks == 0) blocks = 8;
+  // block classes when the average table fits well inside one XCD's L2
+  const uint32_t classes = (total_items / T) * sizeof(TableRow) <= (1u << 20) ? 1u : 0u;
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(64), 0, st, status, (int32_t)ALIAS_OK);
   if (rows)
     hipLaunchKernelGGL(k_sample_batched<true>, dim3((uint32_t)blocks), dim3(kSampleThreads), 0, st,
                        nullptr, nullptr, rows, offsets, draw_off, T, total_items, total_draws,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), out, status);
+                       (uint32_t)seed, (uint32_t)(seed >> 32), classes, out, status);
   else
     hipLaunchKernelGGL(k_sample_batched<false>, dim3((uint32_t)blocks), dim3(kSampleThreads), 0,
                        st, prob, alias, nullptr, offsets, draw_off, T, total_items, total_draws,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), out, status);
+                       (uint32_t)seed, (uint32_t)(seed >> 32), classes, out, status);
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
 

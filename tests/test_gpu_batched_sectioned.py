@@ -298,3 +298,25 @@ def test_batched_sectioned_full_size(name, log2r):
         op, oa = tabs[t]
         ref, _ = oracle.sample_sectioned(op, oa, de - ds, seed, log2r, table=t)
         assert np.array_equal(out[ds:de].cpu().numpy().view(np.uint32), ref), t
+
+
+def test_batched_sectioned_chi_squared():
+    """Batched sectioned draws of a few tables (4e7 draws in all, sections of
+    2^8 rows) fit each table's w / W (grouped chi-squared per table)."""
+    sizes = np.array([300, 70_000, 5000, 1], dtype=np.int64)
+    w = inputs.batch_lognormal(sizes, seed=61, sigma=1.0)
+    off = inputs.offsets_from_sizes(sizes)
+    draws = np.array([3_000_000, 30_000_000, 6_999_999, 1], dtype=np.int64)
+    doff = inputs.offsets_from_sizes(draws)
+    p, a = oracle_tables(w, off, 256)
+    say("batched sectioned chi2")
+    got, st = run(p, a, off, doff, 4321, 8, True)
+    assert st == 0
+    for t in range(len(sizes)):
+        s, e = int(off[t]), int(off[t + 1])
+        ds, de = int(doff[t]), int(doff[t + 1])
+        c = np.bincount(got[ds:de].astype(np.int64), minlength=e - s)
+        assert c.size == e - s and c.sum() == de - ds
+        if e - s > 1:
+            stat, dof, pv = oracle.chi2_gof(c, (de - ds) * w[s:e] / w[s:e].sum())
+            assert pv >= 1e-3, (t, stat, dof, pv)

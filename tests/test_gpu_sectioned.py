@@ -98,3 +98,28 @@ def test_sectioned_full_size_windows():
         for j in sorted(set(rng.integers(0, k, 300).tolist()) | {0, k - 1}):
             exp = oracle.sectioned_draw(p, a, inputs.SAMPLE_SEED, log2r, s, j)
             assert int(got[j]) == exp, (s, j)
+
+
+@pytest.mark.parametrize("log2r", [8, 12])
+def test_sectioned_chi_squared_1e8(log2r):
+    """10^8 sectioned draws (four launches of 2.5e7 with different table ids,
+    so independent streams) from the oracle's table of the 2^20 uniform
+    workload fit w / W (grouped chi-squared, p >= 1e-3)."""
+    w = inputs.make_weights("uniform_2p20")
+    p, a = oracle.psa_build(w, chunk=1024)
+    n = len(w)
+    rows = torch.zeros((n, 4), dtype=torch.int32, device=DEV)
+    rows.view(torch.float64)[:, 0] = torch.from_numpy(p).to(DEV)
+    rows[:, 2] = torch.from_numpy(a.view(np.int32)).to(DEV)
+    say("sectioned chi2", log2r)
+    per = 25_000_000
+    ss = pkg.SectionedSampler(n, per, log2r, device=DEV)
+    counts = torch.zeros(n, dtype=torch.int64, device=DEV)
+    for k in range(4):
+        out = ss.sample_rows(rows, inputs.SAMPLE_SEED, k)
+        counts += torch.bincount(out.long(), minlength=n)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy()
+    assert c.sum() == 10**8
+    stat, dof, pv = oracle.chi2_gof(c, 1e8 * w / w.sum())
+    assert pv >= 1e-3, (stat, dof, pv)
