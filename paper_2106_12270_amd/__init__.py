@@ -13,6 +13,7 @@ __all__ = [
     "AliasError", "lib", "BuildOpts", "WsLayout", "workspace_bytes", "layout", "build",
     "sample", "build_rows", "sample_rows", "rows_split", "Builder", "status_str",
     "BatchBuilder", "sample_batched", "sample_batched_rows", "SectionedSampler",
+    "BatchedSectionedSampler", "default_section_log2",
     "SPLIT_BINARY", "SPLIT_LEARNED", "SPLIT_PARY", "ALIAS_OK",
     "ALIAS_EINVAL", "ALIAS_EWEIGHTS", "ALIAS_EWORKSPACE", "ALIAS_EHIP", "ALIAS_EMODEL",
 ]

@@ -1,6 +1,6 @@
 // C entry points of the alias-table library (declared in alias_mi355x.h).
 // Argument checking and launch plumbing only: all work happens in the
-// kernels of build.hip and sample.hip.
+// kernels of build.hip, sample.hip, sample_sections.hip and learn.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
