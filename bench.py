@@ -14,6 +14,7 @@ on the launch stream during the timed steps.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -88,6 +89,15 @@ def measured_traffic(workload, layout, kernel, launches_per_unit=1.0):
             parts = line.split()
             return (float(parts[-4]) + float(parts[-3])) * 1e9
     return None
+
+
+def device_info(torch):
+    """The facts of the device the numbers were taken on."""
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": p.gcnArchName.split(":")[0],
+            "compute_units": p.multi_processor_count, "warp_size": p.warp_size,
+            "hbm_gib": round(p.total_memory / 2**30, 1), "l2_bytes": p.L2_cache_size,
+            "lds_bytes_per_block": p.shared_memory_per_block}
 
 
 def cpu_baseline(name, cpu_n, draws_sample):
@@ -167,7 +177,10 @@ def learned_vs_binary(pkg, inputs, reps=20, epochs=400, segments=4096):
         bl = pkg.Builder(n, chunk, "learned", model, device=dev)
         t_build_bin = timed(lambda: b.build_rows(w, rows), 5)
         t_build_lrn = timed(lambda: bl.build_rows(w, rows), 5)
+        hh = int(b.header().H)
         out[variant] = {
+            "coarse_round_trips_binary": math.ceil(math.log2(hh / 64 + 2)),
+            "coarse_round_trips_learned": 2 + math.ceil(math.log2(2 * eps + 1)),
             "fit_ms": round(fit_ms, 3), "final_loss": float(loss.item()), "eps": eps,
             "split_ms_binary": round(t_bin, 4), "split_ms_learned": round(t_lrn, 4),
             "split_speedup": round(t_bin / t_lrn, 3), "fallbacks": fallbacks,
@@ -468,6 +481,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "dist": cfg["dist"],
                    "alpha": cfg.get("alpha"), "chunk": chunk, "split": "binary",
                    "draws": draws, "layout": args.layout, "parallelism": "none (1 GPU)"},
+        "device": device_info(torch),
         "build_ms": b_ms,
         "build_hbm_frac": round(build_gbs / HBM_PEAK_GBS, 4),
         "build_gbs": round(build_gbs, 1),
