@@ -306,6 +306,16 @@ def test_philox_matches_rocrand(oracle, rocrand_philox):
         assert tuple(int(v) for v in oracle.philox(b[:4], b[4:])) == r
 
 
+def test_philox_known_answers(oracle):
+    """The published Philox4x32-10 known-answer vectors (tests/golden)."""
+    path = os.path.join(HERE, "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert [int(x) for x in oracle.philox(v[:4], v[4:6])] == v[6:10]
+
+
 def test_sampler_counter_layout_against_rocrand(oracle, rocrand_philox):
     # A table whose rows all keep their item (prob 1) exposes the row map:
     # draw t of table tau uses counter (t lo, t hi, tau, 0), key (seed lo, seed hi)
