@@ -44,7 +44,7 @@ def parse():
                     help="skip the learned-vs-binary split comparison")
     ap.add_argument("--no-sectioned", action="store_true",
                     help="skip the sectioned-sampling measurement")
-    ap.add_argument("--sectioned-log2r", default="13,14,16",
+    ap.add_argument("--sectioned-log2r", default="12,13,16",
                     help="section sizes (log2 rows) of the sectioned-sampling measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched-table workloads (profiling)")

@@ -195,7 +195,9 @@ int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t s
  *      exactly as alias_sample.
  * The output holds `count` independent draws from the table grouped by
  * section (not in the order of alias_sample's stream), bit-reproducible
- * from (table, count, seed, table_id, log2r).
+ * from (table, count, seed, table_id, log2r).  Sections of up to 2^13 rows
+ * are copied into LDS and drawn from there (the paper's shared-memory
+ * sectioned method); larger ones gather from L2.  The result is the same.
  * ------------------------------------------------------------------------ */
 
 /* Workspace bytes (0 if invalid: n not in [1, 2^32 - 1], log2r not in

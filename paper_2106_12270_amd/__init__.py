@@ -610,9 +610,11 @@ def sample_batched_rows(rows, offsets, draw_offsets, seed, out, status=None, str
 # ---------------------------------------------------------------------------
 # Sectioned sampling
 # ---------------------------------------------------------------------------
-def default_section_log2(n, max_sections=8192):
+def default_section_log2(n, max_sections=32768):
     """Smallest section size 2^r (r >= 6) that leaves at most `max_sections`
-    sections (the counts then fit the counting kernel's LDS histogram)."""
+    sections (the counts then fit the counting kernel's LDS histogram).  Up
+    to 2^28 rows this gives sections of at most 2^13 rows, which the drawing
+    kernel stages in LDS."""
     r = 6
     while (int(n) + (1 << r) - 1) >> r > max_sections:
         r += 1

@@ -30,11 +30,14 @@
 //   k_bs_count        all tables' virtual draws -> per-section counts; a
 //                     block takes a contiguous range of pairs and counts in
 //                     an LDS histogram over the sections that range can hit
-//   k_bs_draw         output chunks of 4096 positions; a position belongs
-//                     to the section whose output range holds it, and gets
-//                     that section's draw j = position - section offset (a
-//                     chunk spanning several sections stages their
-//                     descriptions in LDS)
+//   k_bs_draw_lds     sections of at most 2^13 rows: a block copies a
+//                     section's rows into LDS and makes all its draws there
+//   k_bs_draw         larger sections: output chunks of 4096 positions; a
+//                     position belongs to the section whose output range
+//                     holds it, and gets that section's draw j = position -
+//                     section offset, gathering its row from L2 (a chunk
+//                     spanning several sections stages their descriptions
+//                     in LDS)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -580,6 +583,61 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
   }
 }
 
+// LDS-staged draws (Sec. 5, the shared-memory sectioned method): one block
+// of 1024 threads takes whole sections, copies the section's rows into LDS
+// once, and makes every draw of the section from there.  The draws are the
+// same as k_bs_draw's (section s's draw j at out[offset_s + j]); only where
+// the rows are read from differs.  Used when a section fits the LDS and the
+// draws are not much fewer than the rows.
+constexpr int kBsLdsThreads = 1024;
+
+template <bool kRows>
+__global__ __launch_bounds__(kBsLdsThreads) void k_bs_draw_lds(
+    const double *__restrict__ prob, const uint32_t *__restrict__ alias,
+    const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t log2r,
+    const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
+    const uint32_t *__restrict__ sec_table, const BsHeader *h, uint64_t total_draws, uint32_t k0,
+    uint32_t k1, uint32_t table_base, uint32_t *__restrict__ out) {
+  extern __shared__ TableRow s_rows[];  // 2^log2r rows
+  const uint64_t S = h->sections;
+  if (h->flags & kBsBadOffsets) {
+    for (uint64_t o = (uint64_t)blockIdx.x * kBsLdsThreads + threadIdx.x; o < total_draws;
+         o += (uint64_t)gridDim.x * kBsLdsThreads)
+      out[o] = 0xFFFFFFFFu;
+    return;
+  }
+  for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {  // uniform over the block
+    const uint64_t cnt = sec_off[s + 1] - sec_off[s];
+    if (cnt == 0) continue;
+    const BsSec q = bs_section(offsets, sec_start, sec_off, s, sec_table[s], log2r, table_base);
+    if (!q.ok) {
+      for (uint64_t j = threadIdx.x; j < cnt; j += kBsLdsThreads) out[q.so + j] = 0xFFFFFFFFu;
+      continue;
+    }
+    __syncthreads();  // the previous section's reads of s_rows are done
+    const uint64_t first = q.a + q.base;
+    for (uint64_t r = threadIdx.x; r < q.Rs; r += kBsLdsThreads) {
+      if (kRows) {
+        s_rows[r] = rows[first + r];
+      } else {
+        TableRow t;
+        t.prob = prob[first + r];
+        t.alias = alias[first + r];
+        t.pad = 0u;
+        s_rows[r] = t;
+      }
+    }
+    __syncthreads();
+    for (uint64_t j = threadIdx.x; j < cnt; j += kBsLdsThreads) {
+      uint64_t row;
+      double coin;
+      bs_setup(q, j, k0, k1, row, coin);
+      const TableRow t = s_rows[row - q.base];
+      out[q.so + j] = (coin < t.prob) ? (uint32_t)row : t.alias;
+    }
+  }
+}
+
 // Largest dynamic LDS allocation of one block on the current device
 // (queried once per device).
 static size_t bs_max_lds() {
@@ -592,6 +650,21 @@ static size_t bs_max_lds() {
         v <= 0)
       v = 65536;
     cache[dev] = (size_t)v;
+  }
+  return cache[dev];
+}
+
+// Compute units of the current device (queried once per device).
+static uint32_t bs_cu_count() {
+  static uint32_t cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cache[dev] = (uint32_t)v;
   }
   return cache[dev];
 }
@@ -664,6 +737,27 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   if (mb == 0) mb = 1;
   hipLaunchKernelGGL(k_bs_chunk_map, dim3((uint32_t)mb), dim3(256), 0, st,
                      (const uint64_t *)sec_off, (const BsHeader *)h, L.chunks, chunk_sec);
+  // LDS-staged draws when a section's rows fit the LDS (at most 2^13 rows)
+  // and the draws are at least a quarter of the rows (each staged row then
+  // serves enough draws to beat one L2 gather per draw)
+  const size_t lds_bytes = ((size_t)1 << log2r) * sizeof(TableRow);
+  const bool use_lds =
+      log2r <= 13 && lds_bytes <= bs_max_lds() && 4 * total_draws >= total_items;
+  if (use_lds) {
+    uint64_t lb = (uint64_t)bs_cu_count() * (log2r <= 12 ? 2 : 1);
+    if (lb > L.S_max) lb = L.S_max;
+    if (rows)
+      hipLaunchKernelGGL(k_bs_draw_lds<true>, dim3((uint32_t)lb), dim3(kBsLdsThreads), lds_bytes,
+                         st, nullptr, nullptr, rows, offsets, log2r, (const uint64_t *)sec_start,
+                         (const uint64_t *)sec_off, (const uint32_t *)sec_table,
+                         (const BsHeader *)h, total_draws, k0, k1, table_base, out);
+    else
+      hipLaunchKernelGGL(k_bs_draw_lds<false>, dim3((uint32_t)lb), dim3(kBsLdsThreads), lds_bytes,
+                         st, prob, alias, nullptr, offsets, log2r, (const uint64_t *)sec_start,
+                         (const uint64_t *)sec_off, (const uint32_t *)sec_table,
+                         (const BsHeader *)h, total_draws, k0, k1, table_base, out);
+    return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
+  }
   // few blocks when sections hold many chunks (single large tables), more
   // when most chunks span several sections (many small tables)
   uint64_t db = draw_blocks;
