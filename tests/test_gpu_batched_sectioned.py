@@ -320,3 +320,46 @@ def test_batched_sectioned_chi_squared():
         if e - s > 1:
             stat, dof, pv = oracle.chi2_gof(c, (de - ds) * w[s:e] / w[s:e].sum())
             assert pv >= 1e-3, (t, stat, dof, pv)
+
+
+def test_max_tables_build_and_sample():
+    """The largest batch the ABI takes: 2^20 tables of 1..3 items, built in
+    one batch and sampled plain and sectioned; sampled tables against the
+    oracle (tables bit for bit on exact inputs, draws bit for bit)."""
+    T = 1 << 20
+    rng = np.random.default_rng(77)
+    sizes = rng.integers(1, 4, T).astype(np.int64)
+    w = rng.integers(1, 1 << 20, int(sizes.sum())).astype(np.float64)
+    off = inputs.offsets_from_sizes(sizes)
+    # make every table's total a multiple of its size: W/n is then an integer
+    # and every sum of the build is exact, so tables compare bit for bit
+    last = off[1:].astype(np.int64) - 1
+    tot = np.add.reduceat(w, off[:-1].astype(np.int64))
+    w[last] += (-tot) % sizes
+    draws = rng.integers(0, 4, T).astype(np.int64)
+    doff = inputs.offsets_from_sizes(draws)
+    total, nd = len(w), int(doff[-1])
+    say("max tables", T, total, nd)
+    od, dd_ = dev_u64(off), dev_u64(doff)
+    bb = pkg.BatchBuilder(T, total, 64, device=DEV)
+    rows = bb.build_rows(torch.from_numpy(w).to(DEV), od)
+    out_p = torch.empty(nd, dtype=torch.int32, device=DEV)
+    out_p, sst = pkg.sample_batched_rows(rows, od, dd_, 5, out_p)
+    bs = pkg.BatchedSectionedSampler(T, total, nd, 6, device=DEV)
+    out_s = torch.empty(nd, dtype=torch.int32, device=DEV)
+    out_s, sst2 = bs.sample_rows(rows, od, dd_, 5, out_s)
+    torch.cuda.synchronize()
+    assert (bb.status == 0).all() and int(sst.item()) == 0 and int(sst2.item()) == 0
+    pr, al = pkg.rows_split(rows)
+    p = pr.cpu().numpy()
+    a = al.cpu().numpy().view(np.uint32)
+    gp, gs = out_p.cpu().numpy().view(np.uint32), out_s.cpu().numpy().view(np.uint32)
+    for t in sorted(set(rng.integers(0, T, 300).tolist()) | {0, T - 1}):
+        s, e = int(off[t]), int(off[t + 1])
+        op, oa = oracle.psa_build(w[s:e], chunk=64)
+        assert np.array_equal(p[s:e], op) and np.array_equal(a[s:e], oa), t
+        ds, de = int(doff[t]), int(doff[t + 1])
+        if de > ds:
+            assert np.array_equal(gp[ds:de], oracle.sample(op, oa, de - ds, 5, first=0, table=t)), t
+            ref, _ = oracle.sample_sectioned(op, oa, de - ds, 5, 6, table=t)
+            assert np.array_equal(gs[ds:de], ref), t
