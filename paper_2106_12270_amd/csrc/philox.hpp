@@ -37,4 +37,14 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
+// floor(x * r / 2^64) for a 64-bit x and a 32-bit r, exactly (the value of
+// the 64 x 64 multiply-high when r < 2^32): with x = xh 2^32 + xl,
+// x r / 2^64 = (xh r + xl r / 2^32) / 2^32, and dropping the fraction of
+// xl r / 2^32 does not change the floor; xh r + (xl r >> 32) < 2^64.
+__device__ __forceinline__ uint64_t mulhi_u64_u32(uint64_t x, uint32_t r) {
+  const uint64_t lo = (uint64_t)(uint32_t)x * r;
+  const uint64_t hi = (x >> 32) * (uint64_t)r;
+  return (hi + (lo >> 32)) >> 32;
+}
+
 }  // namespace amdalias

@@ -26,7 +26,7 @@ __device__ __forceinline__ void draw_setup(uint64_t t, uint32_t table, uint32_t 
   c.w = 0u;
   const u32x4 r = philox4x32_10(c, k0, k1);
   const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-  row = __umul64hi(x, n);
+  row = mulhi_u64_u32(x, (uint32_t)n);  // n < 2^32
   const uint64_t u = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
   coin = (double)u * 0x1p-53;
 }

@@ -392,8 +392,8 @@ __global__ __launch_bounds__(kBsCountThreads) void k_bs_count(
     const u32x4 r = philox4x32_10(cc, k0, k1);
     const uint64_t x0 = (uint64_t)r.x | ((uint64_t)r.y << 32);
     const uint64_t x1 = (uint64_t)r.z | ((uint64_t)r.w << 32);
-    const uint64_t s0 = ss + (__umul64hi(x0, n) >> log2r);
-    const uint64_t s1 = ss + (__umul64hi(x1, n) >> log2r);
+    const uint64_t s0 = ss + (mulhi_u64_u32(x0, (uint32_t)n) >> log2r);  // n < 2^32
+    const uint64_t s1 = ss + (mulhi_u64_u32(x1, (uint32_t)n) >> log2r);
     const bool two = 2 * b + 1 < c;
     if (lds) {
       atomicAdd(&hist[s0 - sbase], 1u);
@@ -467,7 +467,7 @@ __device__ __forceinline__ void bs_setup(const BsSec &q, uint64_t j, uint32_t k0
   cc.w = q.w;
   const u32x4 r = philox4x32_10(cc, k0, k1);
   const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-  row = q.base + __umul64hi(x, q.Rs);
+  row = q.base + mulhi_u64_u32(x, (uint32_t)q.Rs);  // Rs <= 2^31
   const uint64_t u = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
   coin = (double)u * 0x1p-53;
 }
