@@ -160,3 +160,56 @@ def test_bad_models_fall_back_and_stay_exact(case):
     assert np.array_equal(it["spill"], ref["spill"])
     if case in ("garbage", "wrong_kind", "short_blob"):
         assert it["header"].split_fallbacks > 0
+
+
+@pytest.mark.parametrize("variant", ["iid", "sorted_desc"])
+def test_full_size_lognormal_2p28_learned(variant):
+    """The 2^28 lognormal(0, 2) workload and its sorted-descending variant in
+    the benchmark's configuration (chunk 1024, PWL 4096, 400 epochs, rows):
+    learned splits equal the binary splits with no fallback, the learned
+    build equals the binary build bit for bit, the table matches the oracle's
+    (aliases equal, probabilities within 2 ulp, invariant 1e-12), and
+    sampled draws from the oracle's table are bit-exact."""
+    name = "lognormal_2p28"
+    cfg = inputs.WORKLOADS[name]
+    n = cfg["n"]
+    w = inputs.make_weights(name)
+    if variant == "sorted_desc":
+        w = inputs.sorted_descending(w)
+    say("full lognormal_2p28", variant)
+    wd = torch.from_numpy(w).to(DEV)
+    b = pkg.Builder(n, cfg["chunk"], device=DEV)
+    rows = torch.empty((n, 4), dtype=torch.int32, device=DEV)
+    b.build_rows(wd, rows)
+    torch.cuda.synchronize()
+    assert int(b.status.item()) == 0
+    ref = b.intermediates()
+    model, _ = b.fit_split_model("pwl", 4096, 400)
+    b.resplit(model)
+    it = b.intermediates()
+    for k in ("split_i", "split_j", "spill"):
+        assert np.array_equal(it[k], ref[k]), k
+    assert it["header"].split_fallbacks == 0
+    bl = pkg.Builder(n, cfg["chunk"], "learned", model, device=DEV)
+    rows_l = torch.empty_like(rows)
+    bl.build_rows(wd, rows_l)
+    torch.cuda.synchronize()
+    assert int(bl.status.item()) == 0
+    assert torch.equal(rows, rows_l)
+    del rows_l, bl, wd
+    say("full lognormal_2p28 oracle", variant)
+    pr, al = pkg.rows_split(rows)
+    p = pr.cpu().numpy()
+    a = al.cpu().numpy().view(np.uint32)
+    op, oa = oracle.psa_build(w, chunk=cfg["chunk"])
+    assert np.array_equal(a, oa)
+    assert np.abs(p.view(np.int64) - op.view(np.int64)).max() <= 2
+    r = oracle.check(w, p, a)
+    assert r["max_rel"] <= 1e-12 and r["zero_violations"] == 0, r
+    rows_o = torch.zeros((n, 4), dtype=torch.int32, device=DEV)
+    rows_o.view(torch.float64)[:, 0] = torch.from_numpy(op).to(DEV)
+    rows_o[:, 2] = torch.from_numpy(oa.view(np.int32)).to(DEV)
+    for first in (0, 10**9 - 100_000):
+        out = pkg.sample_rows(rows_o, 100_000, inputs.SAMPLE_SEED, first_draw=first)
+        assert np.array_equal(out.cpu().numpy().view(np.uint32),
+                              oracle.sample(op, oa, 100_000, inputs.SAMPLE_SEED, first=first))
