@@ -18,7 +18,12 @@
  *     spill, independent per-section packing (Sec. 2.2, "Parallel
  *     Construction"; Sec. 4.1 split; Sec. 4.2 pack, whose loop body is the
  *     sequential sweep "if w <= W/N ... else ...");
- *   - baseline sampling, one draw per thread (Sec. 5).
+ *   - baseline sampling, one draw per thread (Sec. 5);
+ *   - sectioned sampling (Sec. 5, the sectioned methods), with the
+ *     per-section draw counts taken exactly from virtual draws instead of
+ *     the paper's normal approximation;
+ *   - the fp64 loss and gradient references of the learned split predictor
+ *     (not in the paper; it only uses binary search, Sec. 4.1).
  *
  * Arithmetic.  Weights, probabilities and the table are IEEE binary64.  The
  * total W, the average W/N, all prefix sums, spills and the running residual
