@@ -363,3 +363,63 @@ def test_max_tables_build_and_sample():
             assert np.array_equal(gp[ds:de], oracle.sample(op, oa, de - ds, 5, first=0, table=t)), t
             ref, _ = oracle.sample_sectioned(op, oa, de - ds, 5, 6, table=t)
             assert np.array_equal(gs[ds:de], ref), t
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_small_batches(case):
+    """Random small batches (empty tables, one-row tables, ragged sizes,
+    tables without draws, every section size and chunk): exact-arithmetic
+    weights, so each table equals the oracle's bit for bit; plain and
+    sectioned batched draws equal the oracle's per table."""
+    rng = np.random.default_rng(1000 + case)
+    T = int(rng.integers(1, 60))
+    sizes = rng.integers(0, 3000, T).astype(np.int64)
+    sizes[rng.random(T) < 0.15] = 0
+    sizes[rng.random(T) < 0.15] = 1
+    if sizes.sum() == 0:
+        sizes[0] = 5
+    off = inputs.offsets_from_sizes(sizes)
+    w = rng.integers(0, 1 << 16, int(sizes.sum())).astype(np.float64)
+    for t in range(T):  # positive totals divisible by the table size: exact W/n
+        s, e = int(off[t]), int(off[t + 1])
+        if e > s:
+            w[e - 1] += 1 + (-(w[s:e].sum() + 1)) % (e - s)
+    draws = np.where(sizes > 0, rng.integers(0, 20_000, T), 0).astype(np.int64)
+    draws[rng.random(T) < 0.2] = 0
+    doff = inputs.offsets_from_sizes(draws)
+    chunk = int(2 ** rng.integers(6, 12))
+    log2r = int(rng.integers(6, 14))
+    seed = int(rng.integers(0, 2**63))
+    total, nd = len(w), int(doff[-1])
+    say("random batch", case, T, total, nd, chunk, log2r)
+    od, dd_ = dev_u64(off), dev_u64(doff)
+    bb = pkg.BatchBuilder(T, total, chunk, device=DEV)
+    rows = bb.build_rows(torch.from_numpy(w).to(DEV), od)
+    outp = torch.full((max(nd, 1),), -5, dtype=torch.int32, device=DEV)[:nd]
+    bs = pkg.BatchedSectionedSampler(T, total, nd, log2r, device=DEV)
+    outs = torch.full((max(nd, 1),), -5, dtype=torch.int32, device=DEV)[:nd]
+    if nd:
+        outp, sp = pkg.sample_batched_rows(rows, od, dd_, seed, outp)
+    outs, ss = bs.sample_rows(rows, od, dd_, seed, outs)
+    torch.cuda.synchronize()
+    st = bb.status.cpu().numpy()
+    pr, al = pkg.rows_split(rows)
+    p = pr.cpu().numpy()
+    a = al.cpu().numpy().view(np.uint32)
+    gp, gs = outp.cpu().numpy().view(np.uint32), outs.cpu().numpy().view(np.uint32)
+    assert int(ss.item()) == 0
+    if nd:
+        assert int(sp.item()) == 0
+    for t in range(T):
+        s, e = int(off[t]), int(off[t + 1])
+        ds, de = int(doff[t]), int(doff[t + 1])
+        if e == s:
+            assert st[t] == pkg.ALIAS_EINVAL  # an empty table is reported, not built
+            continue
+        assert st[t] == 0, t
+        op, oa = oracle.psa_build(w[s:e], chunk=chunk)
+        assert np.array_equal(p[s:e], op) and np.array_equal(a[s:e], oa), t
+        if de > ds:
+            assert np.array_equal(gp[ds:de], oracle.sample(op, oa, de - ds, seed, first=0, table=t)), t
+            ref, _ = oracle.sample_sectioned(op, oa, de - ds, seed, log2r, table=t)
+            assert np.array_equal(gs[ds:de], ref), t
