@@ -365,7 +365,7 @@ def test_max_tables_build_and_sample():
             assert np.array_equal(gs[ds:de], ref), t
 
 
-@pytest.mark.parametrize("case", range(12))
+@pytest.mark.parametrize("case", range(40))
 def test_random_small_batches(case):
     """Random small batches (empty tables, one-row tables, ragged sizes,
     tables without draws, every section size and chunk): exact-arithmetic
