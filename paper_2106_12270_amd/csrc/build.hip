@@ -18,7 +18,8 @@
 //                    Arrays"); prefix sums emitted every 64 entries.
 //   k_split          per section boundary: lights used, heavies closed and
 //                    spill after m = k*C rows (Sec. 2.2; Sec. 4.1 binary
-//                    search baseline), or the learned variant.
+//                    search baseline), the partial p-ary search (Sec. 4.1,
+//                    Alg. 1) or the learned variant.
 //   k_pack           one block per section: the sweep of Sec. 4.2 as a merge
 //                    of two sorted sequences, in LDS.
 // A tile, section or boundary finds its table by binary search over the

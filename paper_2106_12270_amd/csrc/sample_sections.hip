@@ -491,8 +491,8 @@ __device__ __forceinline__ uint32_t bs_pick(const double *__restrict__ prob,
 template <bool kRows>
 __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
     const double *__restrict__ prob, const uint32_t *__restrict__ alias,
-    const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t T,
-    uint32_t log2r, const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
+    const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t log2r,
+    const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
     const uint32_t *__restrict__ sec_table, const uint32_t *__restrict__ chunk_sec,
     const BsHeader *h, uint64_t total_draws, uint32_t k0, uint32_t k1, uint32_t table_base,
     uint32_t *__restrict__ out) {
@@ -769,13 +769,13 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   if (db == 0) db = 8;
   if (rows)
     hipLaunchKernelGGL(k_bs_draw<true>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, nullptr,
-                       nullptr, rows, offsets, T, log2r, (const uint64_t *)sec_start,
+                       nullptr, rows, offsets, log2r, (const uint64_t *)sec_start,
                        (const uint64_t *)sec_off, (const uint32_t *)sec_table,
                        (const uint32_t *)chunk_sec, (const BsHeader *)h, total_draws, k0, k1,
                        table_base, out);
   else
     hipLaunchKernelGGL(k_bs_draw<false>, dim3((uint32_t)db), dim3(kBsThreads), 0, st, prob, alias,
-                       nullptr, offsets, T, log2r, (const uint64_t *)sec_start,
+                       nullptr, offsets, log2r, (const uint64_t *)sec_start,
                        (const uint64_t *)sec_off, (const uint32_t *)sec_table,
                        (const uint32_t *)chunk_sec, (const BsHeader *)h, total_draws, k0, k1,
                        table_base, out);
