@@ -60,6 +60,7 @@ constexpr int kBsThreads = 256;             // count and draw kernels
 constexpr int kBsPer = ALIAS_BS_PER;        // output positions per thread per chunk
 constexpr uint64_t kBsChunk = (uint64_t)kBsThreads * kBsPer;
 constexpr int kBsCountThreads = 1024;    // count kernel
+constexpr uint64_t kBsLdsWork = 1u << 16; // draws per work item of the LDS drawing kernel
 constexpr uint32_t kBsHistMax = 32768;   // sections a count block can histogram in LDS (128 KB)
 constexpr int kBsScanThreads = 1024;     // scan kernels
 constexpr int kBsScanPer = 4;            // consecutive items per scan thread
@@ -79,7 +80,8 @@ struct Two {
 };
 
 struct BsLayout {
-  uint64_t sec_start, pair_start, bsum, bpre, counts, sec_off, sec_table, chunk_sec, total;
+  uint64_t sec_start, pair_start, bsum, bpre, counts, sec_off, sec_work, sec_table, chunk_sec,
+      total;
   uint64_t S_max, nb_max, chunks;
 };
 
@@ -106,6 +108,7 @@ inline bool bs_layout(uint32_t T, uint64_t total_items, uint64_t total_draws, ui
   L->bpre = take(L->nb_max * sizeof(Two));
   L->counts = take(L->S_max * 8);
   L->sec_off = take((L->S_max + 1) * 8);
+  L->sec_work = take((L->S_max + 1) * 8);
   L->chunks = (total_draws + kBsChunk - 1) / kBsChunk;
   L->sec_table = take(L->S_max * 4);
   L->chunk_sec = take((L->chunks + 1) * 4);
@@ -206,15 +209,26 @@ struct TableSrc {
   }
 };
 
+// per section: its count (-> output offsets) and how many work items of
+// kBsLdsWork draws it holds beyond its first (-> first extra work item)
 struct SectionSrc {
   const uint64_t *counts;
   const BsHeader *h;
-  uint64_t *sec_off;
+  uint64_t *sec_off, *sec_work;
   __device__ uint64_t size() const { return h->sections; }
-  __device__ Two value(uint64_t s) const { return Two{counts[s], 0}; }
+  __device__ Two value(uint64_t s) const {
+    const uint64_t c = counts[s];
+    return Two{c, c ? (c - 1) / kBsLdsWork : 0};
+  }
   __device__ uint32_t flags(uint64_t) const { return 0u; }
-  __device__ void put(uint64_t s, Two ex) const { sec_off[s] = ex.a; }
-  __device__ void total(Two s) const { sec_off[h->sections] = s.a; }
+  __device__ void put(uint64_t s, Two ex) const {
+    sec_off[s] = ex.a;
+    sec_work[s] = ex.b;
+  }
+  __device__ void total(Two s) const {
+    sec_off[h->sections] = s.a;
+    sec_work[h->sections] = s.b;
+  }
 };
 
 // this thread's kBsScanPer consecutive items of block `blk` and their sum
@@ -583,21 +597,69 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
   }
 }
 
-// LDS-staged draws (Sec. 5, the shared-memory sectioned method): one block
-// of 1024 threads takes whole sections, copies the section's rows into LDS
-// once, and makes every draw of the section from there.  The draws are the
-// same as k_bs_draw's (section s's draw j at out[offset_s + j]); only where
-// the rows are read from differs.  Used when a section fits the LDS and the
-// draws are not much fewer than the rows.
+// LDS-staged draws (Sec. 5, the shared-memory sectioned method): a block of
+// 1024 threads takes a work item, up to kBsLdsWork consecutive draws of one
+// section, copies the section's rows into LDS and makes those draws from
+// there.  Every section's first work item is taken in section order; the
+// further items of sections with more draws are spread over the grid after
+// that, found through their prefix sums.  The draws are the same as
+// k_bs_draw's (section s's draw j at out[offset_s + j]); only where the rows
+// are read from differs.  Used when a section fits the LDS and the draws are
+// not much fewer than the rows.
 constexpr int kBsLdsThreads = 1024;
 
+// draws [j0, j1) of section s; called by every thread of the block
 template <bool kRows>
-__global__ __launch_bounds__(kBsLdsThreads) void k_bs_draw_lds(
+__device__ __forceinline__ void bs_lds_part(const double *__restrict__ prob,
+                                            const uint32_t *__restrict__ alias,
+                                            const TableRow *__restrict__ rows,
+                                            const uint64_t *__restrict__ offsets, uint32_t log2r,
+                                            const uint64_t *__restrict__ sec_start,
+                                            const uint64_t *__restrict__ sec_off,
+                                            const uint32_t *__restrict__ sec_table, uint64_t s,
+                                            uint64_t j0, uint64_t j1, uint32_t k0, uint32_t k1,
+                                            uint32_t table_base, TableRow *s_rows,
+                                            uint32_t *__restrict__ out) {
+  const BsSec q = bs_section(offsets, sec_start, sec_off, s, sec_table[s], log2r, table_base);
+  if (!q.ok) {
+    for (uint64_t j = j0 + threadIdx.x; j < j1; j += kBsLdsThreads) out[q.so + j] = 0xFFFFFFFFu;
+    return;
+  }
+  __syncthreads();  // the previous item's reads of s_rows are done
+  const uint64_t first = q.a + q.base;
+  for (uint64_t r = threadIdx.x; r < q.Rs; r += kBsLdsThreads) {
+    if (kRows) {
+      s_rows[r] = rows[first + r];
+    } else {
+      TableRow t;
+      t.prob = prob[first + r];
+      t.alias = alias[first + r];
+      t.pad = 0u;
+      s_rows[r] = t;
+    }
+  }
+  __syncthreads();
+  for (uint64_t j = j0 + threadIdx.x; j < j1; j += kBsLdsThreads) {
+    uint64_t row;
+    double coin;
+    bs_setup(q, j, k0, k1, row, coin);
+    const TableRow t = s_rows[row - q.base];
+    out[q.so + j] = (coin < t.prob) ? (uint32_t)row : t.alias;
+  }
+}
+
+// Two of these blocks share a CU only at 8 waves per SIMD, which gfx950
+// grants only to waves of at most 80 SGPRs (more halve the resident waves;
+// measured, while the compiler's occupancy estimate still reports 8): the
+// cap keeps the kernel there, at the price of a few SGPRs kept in VGPR lanes.
+template <bool kRows>
+__global__ __launch_bounds__(kBsLdsThreads) __attribute__((amdgpu_num_sgpr(80))) void k_bs_draw_lds(
     const double *__restrict__ prob, const uint32_t *__restrict__ alias,
     const TableRow *__restrict__ rows, const uint64_t *__restrict__ offsets, uint32_t log2r,
     const uint64_t *__restrict__ sec_start, const uint64_t *__restrict__ sec_off,
-    const uint32_t *__restrict__ sec_table, const BsHeader *h, uint64_t total_draws, uint32_t k0,
-    uint32_t k1, uint32_t table_base, uint32_t *__restrict__ out) {
+    const uint64_t *__restrict__ sec_work, const uint32_t *__restrict__ sec_table,
+    const BsHeader *h, uint64_t total_draws, uint32_t k0, uint32_t k1, uint32_t table_base,
+    uint32_t *__restrict__ out) {
   extern __shared__ TableRow s_rows[];  // 2^log2r rows
   const uint64_t S = h->sections;
   if (h->flags & kBsBadOffsets) {
@@ -606,35 +668,23 @@ __global__ __launch_bounds__(kBsLdsThreads) void k_bs_draw_lds(
       out[o] = 0xFFFFFFFFu;
     return;
   }
-  for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {  // uniform over the block
-    const uint64_t cnt = sec_off[s + 1] - sec_off[s];
-    if (cnt == 0) continue;
-    const BsSec q = bs_section(offsets, sec_start, sec_off, s, sec_table[s], log2r, table_base);
-    if (!q.ok) {
-      for (uint64_t j = threadIdx.x; j < cnt; j += kBsLdsThreads) out[q.so + j] = 0xFFFFFFFFu;
-      continue;
-    }
-    __syncthreads();  // the previous section's reads of s_rows are done
-    const uint64_t first = q.a + q.base;
-    for (uint64_t r = threadIdx.x; r < q.Rs; r += kBsLdsThreads) {
-      if (kRows) {
-        s_rows[r] = rows[first + r];
-      } else {
-        TableRow t;
-        t.prob = prob[first + r];
-        t.alias = alias[first + r];
-        t.pad = 0u;
-        s_rows[r] = t;
-      }
-    }
-    __syncthreads();
-    for (uint64_t j = threadIdx.x; j < cnt; j += kBsLdsThreads) {
-      uint64_t row;
-      double coin;
-      bs_setup(q, j, k0, k1, row, coin);
-      const TableRow t = s_rows[row - q.base];
-      out[q.so + j] = (coin < t.prob) ? (uint32_t)row : t.alias;
-    }
+  // first work items (loop bounds are uniform over the block)
+  for (uint64_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const uint64_t c = sec_off[s + 1] - sec_off[s];
+    if (c == 0) continue;
+    bs_lds_part<kRows>(prob, alias, rows, offsets, log2r, sec_start, sec_off, sec_table, s, 0,
+                       c < kBsLdsWork ? c : kBsLdsWork, k0, k1, table_base, s_rows, out);
+  }
+  // extra work items: item e is part e - sec_work[s] + 1 of the section s
+  // with sec_work[s] <= e < sec_work[s + 1]
+  const uint64_t E = sec_work[S];
+  for (uint64_t e = blockIdx.x; e < E; e += gridDim.x) {
+    const uint64_t s = find_le(sec_work, 0, S, e);
+    const uint64_t c = sec_off[s + 1] - sec_off[s];
+    const uint64_t j0 = (e - sec_work[s] + 1) * kBsLdsWork;
+    const uint64_t j1 = j0 + kBsLdsWork < c ? j0 + kBsLdsWork : c;
+    bs_lds_part<kRows>(prob, alias, rows, offsets, log2r, sec_start, sec_off, sec_table, s, j0,
+                       j1, k0, k1, table_base, s_rows, out);
   }
 }
 
@@ -691,6 +741,7 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   uint64_t *sec_start = (uint64_t *)(ws + L.sec_start), *pair_start = (uint64_t *)(ws + L.pair_start);
   Two *bsum = (Two *)(ws + L.bsum), *bpre = (Two *)(ws + L.bpre);
   uint64_t *counts = (uint64_t *)(ws + L.counts), *sec_off = (uint64_t *)(ws + L.sec_off);
+  uint64_t *sec_work = (uint64_t *)(ws + L.sec_work);
   uint32_t *sec_table = (uint32_t *)(ws + L.sec_table), *chunk_sec = (uint32_t *)(ws + L.chunk_sec);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 
@@ -724,7 +775,7 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   if (counts_out)
     hipLaunchKernelGGL(k_bs_copy_counts, dim3((uint32_t)zb), dim3(256), 0, st,
                        (const uint64_t *)counts, (const BsHeader *)h, counts_out);
-  const SectionSrc ss{(const uint64_t *)counts, h, sec_off};
+  const SectionSrc ss{(const uint64_t *)counts, h, sec_off, sec_work};
   const uint32_t nbs = (uint32_t)((L.S_max + kBsScanBlock - 1) / kBsScanBlock);
   hipLaunchKernelGGL(k_bs_scan_reduce<SectionSrc>, dim3(nbs), dim3(kBsScanThreads), 0, st, ss,
                      bsum, h);
@@ -744,18 +795,23 @@ int launch_sample_batched_sectioned(const double *prob, const uint32_t *alias,
   const bool use_lds =
       log2r <= 13 && lds_bytes <= bs_max_lds() && 4 * total_draws >= total_items;
   if (use_lds) {
+    // at most S_max first and total_draws / kBsLdsWork extra work items
     uint64_t lb = (uint64_t)bs_cu_count() * (log2r <= 12 ? 2 : 1);
-    if (lb > L.S_max) lb = L.S_max;
+    const uint64_t wmax = L.S_max + total_draws / kBsLdsWork;
+    if (lb > wmax) lb = wmax;
+    if (lb == 0) lb = 1;
     if (rows)
       hipLaunchKernelGGL(k_bs_draw_lds<true>, dim3((uint32_t)lb), dim3(kBsLdsThreads), lds_bytes,
                          st, nullptr, nullptr, rows, offsets, log2r, (const uint64_t *)sec_start,
-                         (const uint64_t *)sec_off, (const uint32_t *)sec_table,
-                         (const BsHeader *)h, total_draws, k0, k1, table_base, out);
+                         (const uint64_t *)sec_off, (const uint64_t *)sec_work,
+                         (const uint32_t *)sec_table, (const BsHeader *)h, total_draws, k0, k1,
+                         table_base, out);
     else
       hipLaunchKernelGGL(k_bs_draw_lds<false>, dim3((uint32_t)lb), dim3(kBsLdsThreads), lds_bytes,
                          st, prob, alias, nullptr, offsets, log2r, (const uint64_t *)sec_start,
-                         (const uint64_t *)sec_off, (const uint32_t *)sec_table,
-                         (const BsHeader *)h, total_draws, k0, k1, table_base, out);
+                         (const uint64_t *)sec_off, (const uint64_t *)sec_work,
+                         (const uint32_t *)sec_table, (const BsHeader *)h, total_draws, k0, k1,
+                         table_base, out);
     return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
   }
   // few blocks when sections hold many chunks (single large tables), more

@@ -132,6 +132,42 @@ def test_batched_sectioned_one_table_equals_single_table():
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("rows", [False, True])
+def test_batched_sectioned_heavy_sections(rows):
+    """Sections holding far more draws than one block takes at a time (the
+    shared-memory method spreads such a section over many blocks): a
+    64-row table with 3 million draws, a one-row table with 400 000, counts
+    on both sides of a multiple of 65536, and light tables beside them."""
+    sizes = np.array([64, 1, 200, 64, 64, 5000, 64], dtype=np.int64)
+    w = inputs.batch_lognormal(sizes, seed=23, sigma=2.0)
+    off = inputs.offsets_from_sizes(sizes)
+    draws = np.array([3_000_000, 400_000, 7, 65_536, 65_537, 131_071, 0], dtype=np.int64)
+    doff = inputs.offsets_from_sizes(draws)
+    p, a = oracle_tables(w, off, 64)
+    seed = 4242
+    say("batched sectioned heavy", rows, int(doff[-1]))
+    got, st = run(p, a, off, doff, seed, 6, rows)
+    assert st == 0
+    check_tables(got, p, a, off, doff, seed, 6)
+
+
+def test_sectioned_single_heavy_section():
+    """One 64-row table (one section) with 2^22 + 3 draws through the
+    single-table entry point."""
+    n, count, log2r = 64, (1 << 22) + 3, 6
+    w = inputs.power_law(n, 1.5, 8)
+    p, a = oracle.psa_build(w, chunk=64)
+    say("sectioned one heavy section", count)
+    sm = pkg.SectionedSampler(n, count, log2r, device=DEV)
+    counts = torch.zeros(1, dtype=torch.int64, device=DEV)
+    out = sm.sample(torch.from_numpy(p).to(DEV), torch.from_numpy(a.view(np.int32)).to(DEV), 31,
+                    table_id=5, counts=counts)
+    torch.cuda.synchronize()
+    ref, cnt = oracle.sample_sectioned(p, a, count, 31, log2r, table=5)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), ref)
+    assert int(counts.item()) == count == int(np.asarray(cnt).sum())
+
+
 def test_batched_sectioned_bad_tables():
     sizes = [10, 0, 20]
     w = inputs.uniform01(30, 2)
