@@ -550,10 +550,15 @@ void oracle_sample(const double *prob, const uint32_t *alias, uint64_t n, uint64
  *      the number of virtual draws whose row lies in section s.  So
  *      (c_0, ..., c_{S-1}) is multinomial with the sections' row shares.
  *   2. Draws.  Section s's draws j = 0 .. c_s - 1 fill out[C_s + j], where
- *      C_s = c_0 + ... + c_{s-1}: Philox block with counter (j mod 2^32,
- *      j div 2^32, table, 2 + 4 s), row = s R + floor(x * R_s / 2^64) for the
- *      first 64-bit word x and R_s rows in the section, coin from the last
- *      two words exactly as a plain draw, out = row or alias[row].
+ *      C_s = c_0 + ... + c_{s-1}.  Draws 2p and 2p+1 share the Philox block
+ *      with counter (p mod 2^32, p div 2^32, table, 2 + 4 s): draw j takes
+ *      the 64-bit word x = r0 + 2^32 r1 (j even) or r2 + 2^32 r3 (j odd).
+ *      As in the sampling step of Sec. 2, one uniform U = x / 2^64 makes the
+ *      whole draw: with R_s rows in the section, the integer part of U R_s
+ *      is the row, row = s R + floor(x R_s / 2^64), and its fractional part,
+ *      (x R_s mod 2^64) / 2^64 truncated to 53 bits, is the coin; out = row
+ *      if coin < prob[row], else alias[row].  (For R_s = 2^k the coin has
+ *      64 - k random bits when k > 11.)
  * The output holds `count` independent draws from the table, grouped by
  * section.  counts (may be NULL) receives c_s as uint64[S].  Returns 0, or
  * -1 for invalid arguments (n == 0, log2r > 31, S > 2^26). */
@@ -588,12 +593,15 @@ uint32_t oracle_sectioned_draw(const double *prob, const uint32_t *alias, uint64
   const uint64_t base = sec * R;
   const uint64_t Rs = (n - base < R) ? n - base : R;
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  uint32_t ctr[4] = {(uint32_t)j, (uint32_t)(j >> 32), table, 2u + 4u * (uint32_t)sec};
+  const uint64_t p = j / 2;
+  uint32_t ctr[4] = {(uint32_t)p, (uint32_t)(p >> 32), table, 2u + 4u * (uint32_t)sec};
   uint32_t r[4];
   oracle_philox4x32_10(ctr, key, r);
-  uint64_t x = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
-  uint64_t k = base + (uint64_t)(((unsigned __int128)x * Rs) >> 64);
-  uint64_t u = ((uint64_t)r[2] | ((uint64_t)r[3] << 32)) >> 11;
+  const int h = (int)(j % 2);
+  uint64_t x = (uint64_t)r[2 * h] | ((uint64_t)r[2 * h + 1] << 32);
+  unsigned __int128 xr = (unsigned __int128)x * Rs;  /* U R_s in units of 2^-64 */
+  uint64_t k = base + (uint64_t)(xr >> 64);           /* integer part: the row */
+  uint64_t u = ((uint64_t)xr) >> 11;                  /* fractional part, 53 bits */
   return ((double)u * 0x1p-53 < prob[k]) ? (uint32_t)k : alias[k];
 }
 

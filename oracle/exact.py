@@ -122,9 +122,12 @@ def sampler_distribution(prob, alias):
 
 def sectioned_distribution(prob, alias, log2r):
     """Exact law of one draw of the sectioned sampler: the section is that of
-    row floor(x*n/2^64), the row inside section s is s*R + floor(x'*R_s/2^64)
-    for an independent uniform 64-bit x', then the coin as in
-    sampler_distribution."""
+    row floor(x*n/2^64); inside section s an independent uniform 64-bit x'
+    gives both the row s*R + floor(x'*R_s/2^64) and the coin, the top 53 bits
+    of (x'*R_s mod 2^64) (the integer and fractional parts of one uniform,
+    Sec. 2).  For the x' of row r that mod is x'*R_s - r*2^64, linear in x',
+    so the coin is below p = prob[k] for x' < ceil((r*2^64 + K*2^11) / R_s)
+    with K = ceil(p*2^53)."""
     n = len(prob)
     R = 1 << log2r
     two64 = 1 << 64
@@ -141,10 +144,11 @@ def sectioned_distribution(prob, alias, log2r):
         p_sec = Fraction(xs_below(base + Rs, n) - xs_below(base, n), two64)
         for k in range(base, base + Rs):
             r = k - base
-            p_row = Fraction(xs_below(r + 1, Rs) - xs_below(r, Rs), two64)
+            x0, x1 = xs_below(r, Rs), xs_below(r + 1, Rs)
             thr = _fr(prob[k]) * (1 << 53)
-            keep = min(max(ceil_div(thr.numerator, thr.denominator), 0), 1 << 53)
-            p_keep = Fraction(keep, 1 << 53)
-            out[k] += p_sec * p_row * p_keep
-            out[alias[k]] += p_sec * p_row * (1 - p_keep)
+            K = min(max(ceil_div(thr.numerator, thr.denominator), 0), 1 << 53)
+            xk = ceil_div(r * two64 + K * (1 << 11), Rs)
+            keep = max(0, min(x1, xk) - x0)
+            out[k] += p_sec * Fraction(keep, two64)
+            out[alias[k]] += p_sec * Fraction(x1 - x0 - keep, two64)
     return out

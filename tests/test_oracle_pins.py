@@ -399,6 +399,33 @@ def test_sectioned_counts_follow_the_virtual_draws(oracle):
     assert int(counts.sum()) == count
 
 
+def test_sectioned_draws_take_one_uniform_each(oracle):
+    """Section draws 2p and 2p+1 are the two 64-bit words of Philox block
+    (p, p>>32, table, 2+4s); each word x is one uniform U = x/2^64 whose
+    integer part of U*R_s is the row and whose fractional part (53 bits) is
+    the coin (Sec. 2).  Recomputed here with Python integers for every draw
+    of a small table whose last section is short."""
+    n, log2r, count, seed, table = 1000, 6, 3001, 99, 2
+    w = inputs.lognormal(n, 1.5, 3)
+    prob, alias = oracle.psa_build(w)
+    out, counts = oracle.sample_sectioned(prob, alias, count, seed, log2r, table=table)
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+    R = 1 << log2r
+    at = 0
+    for s, c in enumerate(counts.tolist()):
+        Rs = min(R, n - s * R)
+        for j in range(c):
+            r = oracle.philox(np.array([j // 2, 0, table, 2 + 4 * s], np.uint32), key)
+            h = j % 2
+            x = int(r[2 * h]) | (int(r[2 * h + 1]) << 32)
+            row = s * R + ((x * Rs) >> 64)
+            u = ((x * Rs) & ((1 << 64) - 1)) >> 11
+            want = row if u * 2.0**-53 < prob[row] else int(alias[row])
+            assert int(out[at + j]) == want, (s, j)
+        at += c
+    assert at == count
+
+
 def test_sectioned_groups_hold_their_sections_rows(oracle):
     n, log2r = 5000, 8
     w = inputs.power_law(n, 1.0, 2)
