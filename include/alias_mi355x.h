@@ -189,10 +189,14 @@ int alias_sample_rows(const void *d_rows, uint64_t n, uint64_t count, uint64_t s
  *      r2 + 2^32 r3; each picks row floor(x * n / 2^64) exactly as a plain
  *      draw, and c_s is the number of virtual draws in section s;
  *   2. section s's draws j = 0 .. c_s - 1 are written to out[C_s + j],
- *      C_s = c_0 + ... + c_{s-1}: Philox block with counter
- *      (j mod 2^32, j div 2^32, table_id, 2 + 4 s), row = s R +
- *      floor(x * R_s / 2^64) with R_s the rows of section s, coin and output
- *      exactly as alias_sample.
+ *      C_s = c_0 + ... + c_{s-1}.  Draws 2p and 2p+1 share the Philox block
+ *      with counter (p mod 2^32, p div 2^32, table_id, 2 + 4 s): draw j takes
+ *      the 64-bit word x = r0 + 2^32 r1 (j even) or r2 + 2^32 r3 (j odd), one
+ *      uniform x / 2^64 as in the sampling step of Sec. 2: with R_s the rows
+ *      of section s, row = s R + floor(x * R_s / 2^64) (the integer part)
+ *      and coin = ((x * R_s mod 2^64) >> 11) * 2^-53 (the fractional part;
+ *      64 - log2r random bits when log2r > 11); the draw is row if
+ *      coin < prob[row], else alias[row].
  * The output holds `count` independent draws from the table grouped by
  * section (not in the order of alias_sample's stream), bit-reproducible
  * from (table, count, seed, table_id, log2r).  Sections of up to 2^13 rows

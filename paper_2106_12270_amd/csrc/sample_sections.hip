@@ -472,18 +472,36 @@ __device__ __forceinline__ BsSec bs_section(const uint64_t *__restrict__ offsets
   return q;
 }
 
-__device__ __forceinline__ void bs_setup(const BsSec &q, uint64_t j, uint32_t k0, uint32_t k1,
-                                         uint64_t &row, double &coin) {
+// Section draws 2p and 2p + 1 share the Philox block with counter
+// (p mod 2^32, p div 2^32, table, 2 + 4 s); draw 2p + h takes its 64-bit
+// word h.  Each word x is one uniform U = x / 2^64 that makes the whole draw
+// (the sampling step of Sec. 2): the integer part of U R_s is the row in the
+// section and the fractional part, the low 64 bits of x R_s truncated to
+// 53, is the coin.
+__device__ __forceinline__ u32x4 bs_block(const BsSec &q, uint64_t p, uint32_t k0, uint32_t k1) {
   u32x4 cc;
-  cc.x = (uint32_t)j;
-  cc.y = (uint32_t)(j >> 32);
+  cc.x = (uint32_t)p;
+  cc.y = (uint32_t)(p >> 32);
   cc.z = q.t;
   cc.w = q.w;
-  const u32x4 r = philox4x32_10(cc, k0, k1);
-  const uint64_t x = (uint64_t)r.x | ((uint64_t)r.y << 32);
-  row = q.base + mulhi_u64_u32(x, (uint32_t)q.Rs);  // Rs <= 2^31
-  const uint64_t u = ((uint64_t)r.z | ((uint64_t)r.w << 32)) >> 11;
-  coin = (double)u * 0x1p-53;
+  return philox4x32_10(cc, k0, k1);
+}
+
+__device__ __forceinline__ void bs_word(const BsSec &q, uint32_t xl, uint32_t xh, uint64_t &row,
+                                        double &coin) {
+  const uint32_t r = (uint32_t)q.Rs;  // Rs <= 2^31
+  const uint64_t a = (uint64_t)xl * r, b = (uint64_t)xh * r;
+  row = q.base + ((b + (a >> 32)) >> 32);  // floor(x Rs / 2^64)
+  const uint64_t frac = (b << 32) + a;     // x Rs mod 2^64
+  coin = (double)(frac >> 11) * 0x1p-53;
+}
+
+// draw j of the section alone (its block, then its word)
+__device__ __forceinline__ void bs_setup(const BsSec &q, uint64_t j, uint32_t k0, uint32_t k1,
+                                         uint64_t &row, double &coin) {
+  const u32x4 r = bs_block(q, j >> 1, k0, k1);
+  const bool odd = (j & 1) != 0;
+  bs_word(q, odd ? r.z : r.x, odd ? r.w : r.y, row, coin);
 }
 
 template <bool kRows>
@@ -534,6 +552,13 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
     if (sf == sl) {
       // one section serves the whole chunk
       const BsSec q = bs_section(offsets, sec_start, sec_off, sf, tf, log2r, table_base);
+      if (!q.ok) {
+        for (uint64_t o = o0 + threadIdx.x; o <= olast; o += kBsThreads) out[o] = 0xFFFFFFFFu;
+        continue;
+      }
+      // each position makes its own draw (its pair's block, its word): in
+      // this L2-gathering kernel sharing the block between the two draws of
+      // a pair measured slower than the Philox work it saves
       uint64_t row[kBsPer];
       double coin[kBsPer];
 #pragma unroll
@@ -545,7 +570,7 @@ __global__ __launch_bounds__(kBsThreads) void k_bs_draw(
       for (int u = 0; u < kBsPer; ++u) {
         const uint64_t o = o0 + (uint64_t)u * kBsThreads + threadIdx.x;
         if (o > olast) continue;
-        out[o] = q.ok ? bs_pick<kRows>(prob, alias, rows, q.a, row[u], coin[u]) : 0xFFFFFFFFu;
+        out[o] = bs_pick<kRows>(prob, alias, rows, q.a, row[u], coin[u]);
       }
       continue;
     }
@@ -639,12 +664,19 @@ __device__ __forceinline__ void bs_lds_part(const double *__restrict__ prob,
     }
   }
   __syncthreads();
-  for (uint64_t j = j0 + threadIdx.x; j < j1; j += kBsLdsThreads) {
-    uint64_t row;
-    double coin;
-    bs_setup(q, j, k0, k1, row, coin);
-    const TableRow t = s_rows[row - q.base];
-    out[q.so + j] = (coin < t.prob) ? (uint32_t)row : t.alias;
+  // pairs of draws, one Philox block each (j0 is even)
+  for (uint64_t p = (j0 >> 1) + threadIdx.x; 2 * p < j1; p += kBsLdsThreads) {
+    const u32x4 r = bs_block(q, p, k0, k1);
+    uint64_t row0, row1;
+    double coin0, coin1;
+    bs_word(q, r.x, r.y, row0, coin0);
+    bs_word(q, r.z, r.w, row1, coin1);
+    const TableRow t0 = s_rows[row0 - q.base];
+    out[q.so + 2 * p] = (coin0 < t0.prob) ? (uint32_t)row0 : t0.alias;
+    if (2 * p + 1 < j1) {
+      const TableRow t1 = s_rows[row1 - q.base];
+      out[q.so + 2 * p + 1] = (coin1 < t1.prob) ? (uint32_t)row1 : t1.alias;
+    }
   }
 }
 
