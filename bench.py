@@ -353,7 +353,7 @@ def _cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this library has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np

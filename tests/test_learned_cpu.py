@@ -1,5 +1,5 @@
 """The fp64 CPU references for the learned split models, pinned by central
-finite differences (they are the judge of the GPU training kernels)."""
+finite differences (the GPU training kernels are checked against them)."""
 import numpy as np
 import pytest
 
