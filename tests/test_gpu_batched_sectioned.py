@@ -168,6 +168,30 @@ def test_sectioned_single_heavy_section():
     assert int(counts.item()) == count == int(np.asarray(cnt).sum())
 
 
+@pytest.mark.parametrize("log2r", [14, 16])
+@pytest.mark.parametrize("rows", [False, True])
+def test_batched_sectioned_l2_paths(log2r, rows):
+    """Sections above 2^13 rows are drawn by the L2-gathering kernel.  The
+    batch makes its three chunk kinds: 2000 tiny tables with 0..2 draws
+    (chunks spanning more than 256 sections), 60 mid-size tables (chunks of
+    a few sections), and three tables of 2^17 + odd rows with many draws
+    (chunks inside one section, starting at odd and even draw offsets)."""
+    rng = np.random.default_rng(1400 + log2r)
+    sizes = np.concatenate([rng.integers(1, 51, 2000), rng.integers(100, 5001, 60),
+                            np.array([(1 << 17) + 3, (1 << 17) + 1001, 1 << 17])]).astype(np.int64)
+    draws = np.concatenate([rng.integers(0, 3, 2000), rng.integers(100, 3001, 60),
+                            np.array([300_001, 123_457, 200_000])]).astype(np.int64)
+    w = inputs.batch_lognormal(sizes, seed=41, sigma=1.2)
+    off = inputs.offsets_from_sizes(sizes)
+    doff = inputs.offsets_from_sizes(draws)
+    p, a = oracle_tables(w, off, 512)
+    seed = 5151 + log2r
+    say("batched sectioned L2 paths", log2r, rows, int(doff[-1]))
+    got, st = run(p, a, off, doff, seed, log2r, rows)
+    assert st == 0
+    check_tables(got, p, a, off, doff, seed, log2r)
+
+
 def test_batched_sectioned_bad_tables():
     sizes = [10, 0, 20]
     w = inputs.uniform01(30, 2)
