@@ -61,7 +61,20 @@ struct Batch {
   uint64_t model_bytes, model_stride;
   uint32_t split_pary;          // partial p-ary split search
   uint64_t tiles_max, secs_max, groups_max;
+  // the table of each tile, section and section boundary, filled by k_maps
+  // when the batch has more than one table (one table: always table 0)
+  uint32_t *tile_tab, *sec_tab, *bnd_tab;
 };
+
+__device__ __forceinline__ uint32_t tile_table(const Batch &B, uint64_t tile) {
+  return B.T > 1 ? B.tile_tab[tile] : 0u;
+}
+__device__ __forceinline__ uint32_t sec_table(const Batch &B, uint64_t sec) {
+  return B.T > 1 ? B.sec_tab[sec] : 0u;
+}
+__device__ __forceinline__ uint32_t bnd_table(const Batch &B, uint64_t bnd) {
+  return B.T > 1 ? B.bnd_tab[bnd] : 0u;
+}
 
 __device__ __forceinline__ void table_range(const Batch &B, uint32_t t, uint64_t &off,
                                             uint64_t &n) {
@@ -249,14 +262,11 @@ __device__ __forceinline__ uint32_t group_tiles(const Batch &B, uint64_t g, uint
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTileThreads) void k_reduce_tile(Batch B) {
   __shared__ dd s_wave[kTileThreads / 64];
-  __shared__ uint32_t s_t;
   __shared__ uint32_t s_bad[kTileThreads / 64];
   if (B.flags[0]) return;
   const uint64_t tile = blockIdx.x;
   if (tile >= B.tile_start[B.T]) return;
-  if (threadIdx.x == 0) s_t = find_table(B.tile_start, B.T, tile);
-  __syncthreads();
-  const uint32_t t = s_t;
+  const uint32_t t = tile_table(B, tile);
   uint64_t off, n;
   table_range(B, t, off, n);
   const uint64_t lbase = (tile - B.tile_start[t]) * kTileItems;
@@ -370,14 +380,11 @@ __global__ __launch_bounds__(256) void k_finalize(Batch B) {
 __global__ __launch_bounds__(kTileThreads) void k_tilesum(Batch B) {
   __shared__ dd s_l[kTileThreads / 64], s_h[kTileThreads / 64];
   __shared__ uint32_t s_c[kTileThreads / 64];
-  __shared__ uint32_t s_t;
   if (B.flags[0]) return;
   const uint64_t tile = blockIdx.x;
   if (tile >= B.tile_start[B.T]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_t = find_table(B.tile_start, B.T, tile);
-  __syncthreads();
-  const uint32_t t = s_t;
+  const uint32_t t = tile_table(B, tile);
   if (B.hdr[t].status != ALIAS_OK) return;
   uint64_t off, n;
   table_range(B, t, off, n);
@@ -571,7 +578,6 @@ struct PartShared {
   uint32_t idx[kTileItems];
   dd wl[kPartWaves], wh[kPartWaves];
   uint32_t cl[kPartWaves], ch[kPartWaves];
-  uint32_t t;
 };
 
 __device__ __forceinline__ int spos(int i) { return i + (i >> 4); }
@@ -582,9 +588,7 @@ __global__ __launch_bounds__(kPartThreads) __attribute__((amdgpu_waves_per_eu(6)
   const uint64_t tile = blockIdx.x;
   if (tile >= B.tile_start[B.T]) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) S.t = find_table(B.tile_start, B.T, tile);
-  __syncthreads();
-  const uint32_t t = S.t;
+  const uint32_t t = tile_table(B, tile);
   if (B.hdr[t].status != ALIAS_OK) return;
   uint64_t off, n;
   table_range(B, t, off, n);
@@ -869,7 +873,7 @@ __global__ __launch_bounds__(256) void k_split(Batch B) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // no lane leaves before the wave's partial p-ary phase
   bool active = b < B.sec_start[B.T] + B.T;
-  const uint32_t t = active ? find_table_bnd(B.sec_start, B.T, b) : 0u;
+  const uint32_t t = active ? bnd_table(B, b) : 0u;
   const alias_ws_header &h = B.hdr[t];
   if (h.status != ALIAS_OK) active = false;
   const uint64_t k = b - (B.sec_start[t] + t);  // table-local boundary
@@ -1056,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_pack(Batch B, TableOut out) {
   const int P = blockDim.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t gsec = blockIdx.x;
   if (gsec >= B.sec_start[B.T]) return;
-  const uint32_t t = find_table(B.sec_start, B.T, gsec);
+  const uint32_t t = sec_table(B, gsec);
   const alias_ws_header &hdr = B.hdr[t];
   if (hdr.status != ALIAS_OK) return;
   const uint32_t chunk = B.chunk;
@@ -1234,6 +1238,22 @@ __global__ __launch_bounds__(256) void k_pack(Batch B, TableOut out) {
   }
 }
 
+// The table of every tile, section and section boundary, so that the
+// kernels after the setup read it instead of each searching the T-entry
+// start arrays (a chain of log2 T dependent loads before a block can start).
+__global__ void k_maps(Batch B) {
+  if (B.flags[0]) return;  // the later kernels do not run either
+  // consistent batch (flags clear): ntile <= tiles_max, nbnd <= secs_max
+  const uint64_t ntile = B.tile_start[B.T], nsec = B.sec_start[B.T], nbnd = nsec + B.T;
+  const uint64_t nx = ntile > nbnd ? ntile : nbnd;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nx;
+       x += (uint64_t)gridDim.x * blockDim.x) {
+    if (x < ntile) B.tile_tab[x] = find_table(B.tile_start, B.T, x);
+    if (x < nsec) B.sec_tab[x] = find_table(B.sec_start, B.T, x);
+    if (x < nbnd) B.bnd_tab[x] = find_table_bnd(B.sec_start, B.T, x);
+  }
+}
+
 __global__ void k_reset_fallbacks(Batch B) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < B.T) B.hdr[t].split_fallbacks = 0;
@@ -1303,6 +1323,9 @@ static Batch make_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n
   B.tiles_max = Lo.tiles_max;
   B.secs_max = Lo.secs_max;
   B.groups_max = Lo.groups_max;
+  B.tile_tab = (uint32_t *)(ws + Lo.tile_tab);
+  B.sec_tab = (uint32_t *)(ws + Lo.sec_tab);
+  B.bnd_tab = (uint32_t *)(ws + Lo.bnd_tab);
   return B;
 }
 
@@ -1313,6 +1336,12 @@ static void launch_setup(const Batch &B, hipStream_t st) {
   if (blocks > 1) {
     hipLaunchKernelGGL(k_setup_groups, dim3(1), dim3(kSetupGroup), 0, st, B, blocks);
     hipLaunchKernelGGL(k_setup_add, dim3(blocks), dim3(kSetupGroup), 0, st, B);
+  }
+  if (B.T > 1) {
+    const uint64_t items = B.tiles_max > B.secs_max ? B.tiles_max : B.secs_max;
+    uint64_t mb = (items + 255) / 256;
+    if (mb > 8192) mb = 8192;
+    hipLaunchKernelGGL(k_maps, dim3((uint32_t)mb), dim3(256), 0, st, B);
   }
 }
 

@@ -63,6 +63,9 @@ struct Layout {
   uint64_t grppre;      // TilePrefix per group: exclusive prefix within its table
   uint64_t sscr;        // setup scratch: uint64[3 * setup blocks]
   uint64_t flags;       // uint32[16]: [0] = inconsistent batch description
+  uint64_t tile_tab;    // uint32 per tile: its table (batches of more than one table)
+  uint64_t sec_tab;     // uint32 per section: its table (same)
+  uint64_t bnd_tab;     // uint32 per section boundary: its table (same)
   uint64_t tiles_max, secs_max, groups_max, total;
   uint32_t T, chunk, pack_waves, split_method;
 };
@@ -115,6 +118,9 @@ inline bool compute_layout_batch(uint32_t T, uint64_t total, const alias_build_o
   L->grp_start = take((T + 1ull) * 8);
   L->flags = take(64);
   L->sscr = take(sblocks * 24 + 24);
+  L->tile_tab = take(tiles * 4);
+  L->sec_tab = take(secs * 4);
+  L->bnd_tab = take(secs * 4);
   L->tilew = take(tiles * sizeof(ReducePart));
   L->grpw = take(grps * sizeof(ReducePart));
   L->tilesum = take(tiles * sizeof(TileSum));
