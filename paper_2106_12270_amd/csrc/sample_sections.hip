@@ -31,7 +31,9 @@
 //                     block takes a contiguous range of pairs and counts in
 //                     an LDS histogram over the sections that range can hit
 //   k_bs_draw_lds     sections of at most 2^13 rows: a block copies a
-//                     section's rows into LDS and makes all its draws there
+//                     section's rows into LDS and makes up to 65536 of its
+//                     draws there, two per Philox block (a section with
+//                     more draws is spread over several blocks)
 //   k_bs_draw         larger sections: output chunks of 4096 positions; a
 //                     position belongs to the section whose output range
 //                     holds it, and gets that section's draw j = position -
