@@ -1329,6 +1329,15 @@ static Batch make_batch(const double *d_w, const uint64_t *d_offsets, uint64_t n
   return B;
 }
 
+// the table maps (batches of more than one table), from the start arrays
+static void launch_maps(const Batch &B, hipStream_t st) {
+  if (B.T <= 1) return;
+  const uint64_t items = B.tiles_max > B.secs_max ? B.tiles_max : B.secs_max;
+  uint64_t mb = (items + 255) / 256;
+  if (mb > 8192) mb = 8192;
+  hipLaunchKernelGGL(k_maps, dim3((uint32_t)mb), dim3(256), 0, st, B);
+}
+
 static void launch_setup(const Batch &B, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, B.flags);
   const uint32_t blocks = (B.T + kSetupGroup - 1) / kSetupGroup;
@@ -1337,12 +1346,7 @@ static void launch_setup(const Batch &B, hipStream_t st) {
     hipLaunchKernelGGL(k_setup_groups, dim3(1), dim3(kSetupGroup), 0, st, B, blocks);
     hipLaunchKernelGGL(k_setup_add, dim3(blocks), dim3(kSetupGroup), 0, st, B);
   }
-  if (B.T > 1) {
-    const uint64_t items = B.tiles_max > B.secs_max ? B.tiles_max : B.secs_max;
-    uint64_t mb = (items + 255) / 256;
-    if (mb > 8192) mb = 8192;
-    hipLaunchKernelGGL(k_maps, dim3((uint32_t)mb), dim3(256), 0, st, B);
-  }
+  launch_maps(B, st);
 }
 
 static void launch_split(const Batch &B, hipStream_t st) {
@@ -1420,6 +1424,7 @@ int launch_split_only(void *d_ws, const uint64_t *d_offsets, uint64_t n1, const 
   Batch B = make_batch(nullptr, d_offsets, n1, d_ws, &hdr->status, Lo, models, model_bytes,
                        model_stride);
   hipLaunchKernelGGL(k_reset_fallbacks, dim3((Lo.T + 255) / 256), dim3(256), 0, st, B);
+  launch_maps(B, st);  // rebuilt from the start arrays, so every table index stays below T
   launch_split(B, st);
   return hipGetLastError() == hipSuccess ? ALIAS_OK : ALIAS_EHIP;
 }
