@@ -332,6 +332,25 @@ class Builder:
         return out
 
 
+def _check_table(prob, alias, n):
+    """A two-array table of at least n rows (the library reads n of each)."""
+    import torch
+
+    _check_dev(prob, torch.float64, "prob")
+    _check_dev(alias, torch.int32, "alias")
+    if prob.numel() < n or alias.numel() < n:
+        raise ValueError(f"prob and alias must hold at least {n} rows")
+
+
+def _check_counts(counts, sections):
+    import torch
+
+    if counts is not None:
+        _check_dev(counts, torch.int64, "counts")
+        if counts.numel() < sections:
+            raise ValueError(f"counts must hold at least {sections} entries")
+
+
 def _check_rows(rows, n):
     import torch
 
@@ -438,8 +457,7 @@ def sample(prob, alias, count, seed, first_draw=0, table_id=0, out=None, stream=
     """Draw `count` samples (int32 tensor holding uint32 item ids)."""
     import torch
 
-    _check_dev(prob, torch.float64, "prob")
-    _check_dev(alias, torch.int32, "alias")
+    _check_table(prob, alias, prob.numel())
     if out is None:
         out = torch.empty(int(count), dtype=torch.int32, device=prob.device)
     _check_dev(out, torch.int32, "out")
@@ -580,10 +598,7 @@ def sample_batched(prob, alias, offsets, draw_offsets, seed, out, status=None, s
     """Draw out.numel() samples over a batch: table t fills
     out[draw_offsets[t]:draw_offsets[t+1]] with table-local ids.  Returns
     (out, status) where status is a 1-element int32 device tensor."""
-    import torch
-
-    _check_dev(prob, torch.float64, "prob")
-    _check_dev(alias, torch.int32, "alias")
+    _check_table(prob, alias, prob.numel())
     T, status = _sample_batched_args(offsets, draw_offsets, prob.numel(), out, status, prob.device)
     st = lib().alias_sample_batched(_ptr(prob), _ptr(alias), _ptr(offsets), T, prob.numel(),
                                     _ptr(draw_offsets), out.numel(), int(seed) & (2**64 - 1),
@@ -646,6 +661,9 @@ class SectionedSampler:
         if out is None:
             out = torch.empty(self.count, dtype=torch.int32, device=rows.device)
         _check_dev(out, torch.int32, "out")
+        if out.numel() < self.count:
+            raise ValueError("out is too small")
+        _check_counts(counts, self.sections)
         st = lib().alias_sample_sectioned_rows(
             _ptr(rows), self.n, self.count, int(seed) & (2**64 - 1), int(table_id), self.log2r,
             _ptr(out), _ptr(counts) if counts is not None else None, _ptr(self.ws),
@@ -657,11 +675,13 @@ class SectionedSampler:
     def sample(self, prob, alias, seed, table_id=0, out=None, counts=None, stream=None):
         import torch
 
-        _check_dev(prob, torch.float64, "prob")
-        _check_dev(alias, torch.int32, "alias")
+        _check_table(prob, alias, self.n)
         if out is None:
             out = torch.empty(self.count, dtype=torch.int32, device=prob.device)
         _check_dev(out, torch.int32, "out")
+        if out.numel() < self.count:
+            raise ValueError("out is too small")
+        _check_counts(counts, self.sections)
         st = lib().alias_sample_sectioned(
             _ptr(prob), _ptr(alias), self.n, self.count, int(seed) & (2**64 - 1), int(table_id),
             self.log2r, _ptr(out), _ptr(counts) if counts is not None else None, _ptr(self.ws),
@@ -709,10 +729,7 @@ class BatchedSectionedSampler:
         return out, self.status
 
     def sample(self, prob, alias, offsets, draw_offsets, seed, out, stream=None):
-        import torch
-
-        _check_dev(prob, torch.float64, "prob")
-        _check_dev(alias, torch.int32, "alias")
+        _check_table(prob, alias, prob.numel())
         T = self._args(offsets, draw_offsets, prob.numel(), out, prob.device)
         st = lib().alias_sample_batched_sectioned(
             _ptr(prob), _ptr(alias), _ptr(offsets), T, prob.numel(), _ptr(draw_offsets),

@@ -123,3 +123,32 @@ def test_sectioned_chi_squared_1e8(log2r):
     assert c.sum() == 10**8
     stat, dof, pv = oracle.chi2_gof(c, 1e8 * w / w.sum())
     assert pv >= 1e-3, (stat, dof, pv)
+
+
+def test_binding_rejects_short_arrays():
+    """The Python entry points check lengths before any launch: a table
+    whose alias array is shorter than its prob array, an output or counts
+    tensor that is too small, or counts of the wrong type."""
+    p = torch.full((100,), 0.5, dtype=torch.float64, device=DEV)
+    a_short = torch.zeros(99, dtype=torch.int32, device=DEV)
+    a = torch.zeros(100, dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError):
+        pkg.sample(p, a_short, 10, 1)
+    off = torch.tensor([0, 100], dtype=torch.int64, device=DEV)
+    doff = torch.tensor([0, 10], dtype=torch.int64, device=DEV)
+    out = torch.empty(10, dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError):
+        pkg.sample_batched(p, a_short, off, doff, 1, out)
+    ss = pkg.SectionedSampler(100, 50, 6, device=DEV)
+    with pytest.raises(ValueError):
+        ss.sample(p, a_short, 1)
+    with pytest.raises(ValueError):
+        ss.sample(p, a, 1, out=torch.empty(49, dtype=torch.int32, device=DEV))
+    with pytest.raises(ValueError):
+        ss.sample(p, a, 1, counts=torch.zeros(1, dtype=torch.int64, device=DEV))  # 2 sections
+    with pytest.raises(TypeError):
+        ss.sample(p, a, 1, counts=torch.zeros(2, dtype=torch.int32, device=DEV))
+    bs = pkg.BatchedSectionedSampler(1, 100, 10, 6, device=DEV)
+    with pytest.raises(ValueError):
+        bs.sample(p, a_short, off, doff, 1, out)
+    torch.cuda.synchronize()
