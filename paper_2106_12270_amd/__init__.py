@@ -233,8 +233,7 @@ class Builder:
             prob = torch.empty(self.n, dtype=torch.float64, device=w.device)
         if alias is None:
             alias = torch.empty(self.n, dtype=torch.int32, device=w.device)
-        _check_dev(prob, torch.float64, "prob")
-        _check_dev(alias, torch.int32, "alias")
+        _check_table(prob, alias, self.n)
         st = lib().alias_build(C.c_void_p(w.data_ptr()), self.n, C.c_void_p(prob.data_ptr()),
                                C.c_void_p(alias.data_ptr()), C.c_void_p(self.ws.data_ptr()),
                                self.ws_bytes, C.c_void_p(self.status.data_ptr()),
@@ -519,8 +518,7 @@ class BatchBuilder:
             prob = torch.empty(self.total, dtype=torch.float64, device=w.device)
         if alias is None:
             alias = torch.empty(self.total, dtype=torch.int32, device=w.device)
-        _check_dev(prob, torch.float64, "prob")
-        _check_dev(alias, torch.int32, "alias")
+        _check_table(prob, alias, self.total)
         st = lib().alias_build_batched(_ptr(w), _ptr(offsets), self.T, self.total, _ptr(prob),
                                        _ptr(alias), _ptr(self.ws), self.ws_bytes,
                                        _ptr(self.status), C.byref(self.opts), _stream(stream))

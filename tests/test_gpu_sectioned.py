@@ -151,4 +151,9 @@ def test_binding_rejects_short_arrays():
     bs = pkg.BatchedSectionedSampler(1, 100, 10, 6, device=DEV)
     with pytest.raises(ValueError):
         bs.sample(p, a_short, off, doff, 1, out)
+    w = torch.ones(100, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):  # output arrays shorter than the table
+        pkg.Builder(100, device=DEV).build(w, p, a_short)
+    with pytest.raises(ValueError):
+        pkg.BatchBuilder(1, 100, device=DEV).build(w, off, p, a_short)
     torch.cuda.synchronize()
