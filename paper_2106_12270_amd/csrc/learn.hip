@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kLearnThreads) void k_loss_partial(const SplitModel
 }
 
 // ---------------------------------------------------------------------------
-// PWL gradient: one thread per knot over the points of its two segments
+// PWL gradient: one wave per knot over the points of its two segments
 // (points sorted by x, so each segment's points are a contiguous range)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pwl_seg(float x, uint32_t K) {
@@ -183,29 +183,44 @@ __device__ __forceinline__ uint32_t first_point_of_seg(const float *x, uint32_t 
   return lo;
 }
 
+// the first point of every segment k = 0..K (K: none, so `points`); the
+// points do not move during a fit, so this runs once per fit
+__global__ void k_pwl_seg_first(const SplitModel *M, const float *__restrict__ x,
+                                uint32_t points, uint32_t *__restrict__ seg_first) {
+  const uint32_t K = M->segments;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k <= K) seg_first[k] = first_point_of_seg(x, points, K, (int)k);
+}
+
+// one wave per knot s: its lanes share the points of the knot's two
+// segments, then a butterfly sum in a fixed order
 __global__ __launch_bounds__(kLearnThreads) void k_pwl_grad(const SplitModel *M,
                                                             const float *__restrict__ x,
                                                             const float *__restrict__ t,
                                                             uint32_t points,
+                                                            const uint32_t *__restrict__ seg_first,
                                                             double *__restrict__ grad) {
   const uint32_t K = M->segments;
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
+  const uint32_t lane = threadIdx.x & 63;
   if (s > K) return;
   const float *p = M->params;
   double acc = 0.0;
   for (int seg = (int)s - 1; seg <= (int)s; ++seg) {
     if (seg < 0 || seg >= (int)K) continue;
-    const uint32_t lo = first_point_of_seg(x, points, K, seg);
-    const uint32_t hi = first_point_of_seg(x, points, K, seg + 1);
-    for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t lo = seg_first[seg], hi = seg_first[seg + 1];
+    const float p0 = p[seg], p1 = p[seg + 1];
+    for (uint32_t i = lo + lane; i < hi; i += 64) {
       const float u = x[i] * (float)K;
       const float f = u - (float)seg;
-      const float y = p[seg] + f * (p[seg + 1] - p[seg]);
+      const float y = p0 + f * (p1 - p0);
       const double r = (double)y - (double)t[i];
       acc += 2.0 * r * (double)((seg == (int)s) ? (1.0f - f) : f);
     }
   }
-  grad[s] = acc / (double)points;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if (lane == 0) grad[s] = acc / (double)points;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,14 +415,24 @@ __global__ void k_model_finish(SplitModel *M, const int32_t *maxerr) {
 // ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
+// seg_fresh: the PWL segment bounds must be (re)computed first (the first
+// gradient of a fit, or a gradient on its own)
 static int launch_grad(uint32_t kind, const SplitModel *M, const float *x, const float *t,
                        uint32_t points, const TrainLayout &T, char *tw, double *grad, double *loss,
-                       hipStream_t st) {
+                       bool seg_fresh, hipStream_t st) {
   double *part = (double *)(tw + T.part), *lpart = (double *)(tw + T.loss_part);
   const uint32_t np = T.nparams;
   if (kind == kModelPWL) {
-    hipLaunchKernelGGL(k_pwl_grad, dim3((np + kLearnThreads - 1) / kLearnThreads),
-                       dim3(kLearnThreads), 0, st, M, x, t, points, grad);
+    // the per-block partials are not used by the PWL gradient: their space
+    // (at least np * 8 bytes) holds the np = K + 1 segment bounds
+    uint32_t *seg_first = (uint32_t *)part;
+    if (seg_fresh)
+      hipLaunchKernelGGL(k_pwl_seg_first, dim3((np + 255) / 256), dim3(256), 0, st, M, x, points,
+                         seg_first);
+    const uint64_t threads = (uint64_t)np * 64;
+    hipLaunchKernelGGL(k_pwl_grad, dim3((uint32_t)((threads + kLearnThreads - 1) / kLearnThreads)),
+                       dim3(kLearnThreads), 0, st, M, x, t, points, (const uint32_t *)seg_first,
+                       grad);
     if (loss) {
       hipLaunchKernelGGL(k_loss_partial, dim3(T.blocks), dim3(kLearnThreads), 0, st, M, x, t,
                          points, lpart);
@@ -636,7 +661,7 @@ int alias_split_model_fit(const void *d_build_ws, uint64_t n, const alias_build_
   double p1 = 1.0, p2 = 1.0;
   for (uint32_t e = 0; e < epochs; ++e) {
     const bool last = (e + 1 == epochs);
-    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, last ? loss : nullptr, st);
+    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, last ? loss : nullptr, e == 0, st);
     if (rc) return rc;
     p1 *= b1;
     p2 *= b2;
@@ -644,7 +669,7 @@ int alias_split_model_fit(const void *d_build_ws, uint64_t n, const alias_build_
                        epochs, (float)(1.0 - p1), (float)(1.0 - p2));
   }
   if (epochs == 0) {
-    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, loss, st);
+    int rc = launch_grad(kind, M, x, t, points, T, tw, grad, loss, true, st);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, maxerr);
@@ -664,7 +689,7 @@ int alias_split_model_grad(uint32_t kind, uint32_t segments, const void *d_model
   if (model_bytes < alias_split_model_bytes(kind, segments)) return ALIAS_EINVAL;
   if (train_ws_bytes < T.total || ((uintptr_t)d_train_ws & 255)) return ALIAS_EWORKSPACE;
   return launch_grad(kind, (const SplitModel *)d_model, d_x, d_t, (uint32_t)points, T,
-                     (char *)d_train_ws, d_grad, d_loss, (hipStream_t)stream);
+                     (char *)d_train_ws, d_grad, d_loss, true, (hipStream_t)stream);
 }
 
 size_t alias_split_model_fit_batched_workspace_bytes(uint32_t T, uint64_t total_items,
