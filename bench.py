@@ -465,6 +465,12 @@ def main():
     if tb is not None and draws == cfg["draws"]:
         roof["traffic"] = round(tb / 1e9, 3)
         roof["traffic_unit"] = "GB per launch"
+        if roof["kernel"].startswith("k_sample"):
+            # the rate of the bytes HBM actually moved (each random gather
+            # moves a whole line, not the 16 B of a row), against the peak
+            traffic_gbs = tb / (s_ms * 1e-3) / 1e9
+            roof["traffic_gbs"] = round(traffic_gbs, 1)
+            roof["traffic_frac"] = round(traffic_gbs / HBM_PEAK_GBS, 4)
     result = {
         "metric": "alias build items/s (%HBM peak) + samples/s; learned vs binary split, 1 GPU",
         "value": n / (b_ms * 1e-3),
