@@ -312,6 +312,7 @@ __global__ __launch_bounds__(256) void k_reduce_group(Batch B) {
   group_tiles(B, g, &k0, &k1);
   dd s = dd_make(0.0, 0.0);
   uint32_t bad = 0;
+#pragma unroll 4  // several tiles' loads in flight; the sum keeps its order
   for (uint64_t k = k0 + lane; k < k1; k += 64) {
     const ReducePart p = B.tilew[k];
     s = add_fast(s, dd_make(p.hi, p.lo));
